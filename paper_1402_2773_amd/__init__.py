@@ -1,0 +1,236 @@
+"""NGDBF LDPC decoding on AMD Instinct MI355X (gfx950).
+
+Python binding of ``libngdbf.so``, whose C ABI is declared in
+``include/ngdbf.h``: Noisy Gradient-Descent Bit-Flip decoding (Sundararajan,
+Winstead, Boutillon, IEEE TCOM 2014, Sec. III) of many frames per call.
+The functions named ``ngdbf_*`` mirror the C entry points one to one and only
+marshal arguments; every step of decoding runs in the library's HIP kernels.
+PyTorch provides device memory and streams.  There is no CPU fallback:
+without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libngdbf.so")
+
+NGDBF_Y_F32 = 0
+NGDBF_Y_I8 = 1
+
+#: names of the C entry points (include/ngdbf.h)
+ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "ngdbf_decode",
+                 "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_last_error")
+
+
+class NgdbfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ngdbf status {status}: {message}")
+        self.status = status
+
+
+class ngdbf_params(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_float), ("theta", ctypes.c_float), ("lam", ctypes.c_float),
+                ("eta", ctypes.c_float), ("ymax", ctypes.c_float), ("t_max", ctypes.c_int32),
+                ("smooth_window", ctypes.c_int32), ("y_format", ctypes.c_int32)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Decoder parameters in the paper's notation (Sec. III-B..E, IV-A)."""
+
+    w: float = 0.75
+    theta: float = -0.6
+    lam: float = 1.0
+    eta: float = 0.9
+    ymax: float = 2.5
+    t_max: int = 100
+    smooth_window: int = 0
+
+    def c(self, y_format: int) -> ngdbf_params:
+        return ngdbf_params(self.w, self.theta, self.lam, self.eta, self.ymax, self.t_max,
+                            self.smooth_window, y_format)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_1402_2773_amd/build.py` (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, U32, U64, F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                    ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float)
+        L.ngdbf_create_code.argtypes = [I32, I32, P, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.ngdbf_destroy_code.argtypes = [P]
+        L.ngdbf_code_info.argtypes = [P, P, P, P]
+        L.ngdbf_decode.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, U64,
+                                   P, P, P, P]
+        L.ngdbf_decode_trace.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64,
+                                         U64, P, P, P, P, P]
+        L.ngdbf_noise_probe.argtypes = [I32, U32, U32, U64, U64, U32, P, P, P]
+        L.ngdbf_last_error.argtypes = []
+        L.ngdbf_last_error.restype = ctypes.c_char_p
+        for name in ABI_FUNCTIONS:
+            if name != "ngdbf_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise NgdbfError(status, lib().ngdbf_last_error().decode())
+
+
+def _addr(x) -> Optional[int]:
+    """Device/host address of a torch tensor or numpy array, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ------------------------------------------------------------- C entry points
+
+def ngdbf_create_code(n: int, m: int, row_ptr, col_idx) -> ctypes.c_void_p:
+    import numpy as np
+
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().ngdbf_create_code(n, m, rp.ctypes.data, ci.ctypes.data, ctypes.byref(h)))
+    return h
+
+
+def ngdbf_destroy_code(code) -> None:
+    _check(lib().ngdbf_destroy_code(code))
+
+
+def ngdbf_code_info(code):
+    n, m, nnz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ngdbf_code_info(code, ctypes.byref(n), ctypes.byref(m), ctypes.byref(nnz)))
+    return n.value, m.value, nnz.value
+
+
+def ngdbf_decode(code, y, n_frames: int, sigma, sigma_scalar: float, params: ngdbf_params,
+                 seed: int, frame_base: int, out_bits, out_iters, out_converged, stream) -> None:
+    _check(lib().ngdbf_decode(code, _addr(y), n_frames, _addr(sigma), sigma_scalar,
+                              ctypes.byref(params), seed, frame_base, _addr(out_bits),
+                              _addr(out_iters), _addr(out_converged), _stream(stream)))
+
+
+def ngdbf_decode_trace(code, y, n_frames: int, sigma, sigma_scalar: float, params: ngdbf_params,
+                       seed: int, frame_base: int, out_bits, out_iters, out_converged,
+                       flip_masks, stream) -> None:
+    _check(lib().ngdbf_decode_trace(code, _addr(y), n_frames, _addr(sigma), sigma_scalar,
+                                    ctypes.byref(params), seed, frame_base, _addr(out_bits),
+                                    _addr(out_iters), _addr(out_converged), _addr(flip_masks),
+                                    _stream(stream)))
+
+
+def ngdbf_noise_probe(kind: int, start: int, count: int, seed: int, frame: int, iteration: int,
+                      out0, out1, stream) -> None:
+    _check(lib().ngdbf_noise_probe(kind, start, count, seed, frame, iteration, _addr(out0),
+                                   _addr(out1), _stream(stream)))
+
+
+def ngdbf_last_error() -> str:
+    return lib().ngdbf_last_error().decode()
+
+
+# ------------------------------------------------------------- conveniences
+
+class Code:
+    """A parity-check matrix resident on the current device (owns the handle)."""
+
+    def __init__(self, n: int, m: int, row_ptr, col_idx):
+        self.n, self.m = int(n), int(m)
+        self.handle = ngdbf_create_code(self.n, self.m, row_ptr, col_idx)
+
+    @classmethod
+    def from_ldpc(cls, code) -> "Code":
+        return cls(code.n, code.m, code.row_ptr, code.col_idx)
+
+    @property
+    def nbytes_row(self) -> int:
+        return (self.n + 7) // 8
+
+    def close(self) -> None:
+        if self.handle is not None and self.handle.value:
+            ngdbf_destroy_code(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class Outputs:
+    bits: "object"       # torch.uint8 [F, ceil(n/8)]
+    iters: "object"      # torch.int32 [F]
+    converged: "object"  # torch.uint8 [F]
+    trace: "object" = None  # torch.uint8 [F, T, ceil(n/8)]
+
+
+def decode(code: Code, y, sigma, params: Params, seed: int, frame_base: int = 0,
+           trace: bool = False, stream=None, out: Optional[Outputs] = None) -> Outputs:
+    """Decode the frames of y (torch [F, n] float32 or int8 on the device).
+
+    sigma: a float, or a torch float32 [F] tensor on the device.  Outputs
+    are allocated on y's device unless ``out`` is given."""
+    import torch
+
+    if y.dim() != 2 or y.shape[1] != code.n:
+        raise ValueError("y must be [frames, n]")
+    if not y.is_contiguous():
+        raise ValueError("y must be contiguous")
+    if y.dtype == torch.float32:
+        fmt = NGDBF_Y_F32
+    elif y.dtype == torch.int8:
+        fmt = NGDBF_Y_I8
+    else:
+        raise ValueError("y must be float32 or int8")
+    F = y.shape[0]
+    if out is None:
+        out = Outputs(torch.empty((F, code.nbytes_row), dtype=torch.uint8, device=y.device),
+                      torch.empty(F, dtype=torch.int32, device=y.device),
+                      torch.empty(F, dtype=torch.uint8, device=y.device))
+        if trace:
+            out.trace = torch.empty((F, params.t_max, code.nbytes_row), dtype=torch.uint8,
+                                    device=y.device)
+    sig_t, sig_s = (sigma, 0.0) if isinstance(sigma, torch.Tensor) else (None, float(sigma))
+    if sig_t is not None and (sig_t.dtype != torch.float32 or sig_t.numel() != F
+                              or not sig_t.is_contiguous()):
+        raise ValueError("sigma must be a contiguous float32 tensor with one value per frame")
+    p = params.c(fmt)
+    if trace:
+        ngdbf_decode_trace(code.handle, y, F, sig_t, sig_s, p, seed, frame_base, out.bits,
+                           out.iters, out.converged, out.trace, stream)
+    else:
+        ngdbf_decode(code.handle, y, F, sig_t, sig_s, p, seed, frame_base, out.bits, out.iters,
+                     out.converged, stream)
+    return out

@@ -1,0 +1,44 @@
+"""Build libngdbf.so (the HIP kernels and the C ABI of include/ngdbf.h) for gfx950.
+
+Flags that the decoder's bit-exact contract depends on:
+  -ffp-contract=off          no fusion of a*b+c beyond the explicit fmaf calls
+  -fno-gpu-flush-denormals-to-zero, no fast-math: IEEE binary32 semantics,
+                             correctly rounded division and square root
+  -target-feature -packed-fp32-ops: keep the compiler from forming packed
+                             fp32 instructions
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libngdbf.so")
+SOURCES = [os.path.join(HERE, "csrc", "decode.hip")]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = os.environ.get("NGDBF_ARCH", "gfx950")
+
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-ffp-contract=off", "-fno-fast-math", "-fno-gpu-flush-denormals-to-zero",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-result",
+    f"-I{os.path.join(ROOT, 'include')}",
+]
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, *SOURCES, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)

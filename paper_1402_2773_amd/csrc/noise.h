@@ -1,0 +1,142 @@
+// noise.h -- the decoder's Gaussian source on gfx950 (device code).
+//
+// Sec. III-C draws q_k ~ N(0, eta^2 N0/2) independently for every bit and
+// round.  The paper leaves the generator open; this library fixes it so
+// that any implementation can reproduce the draws bit for bit:
+//
+//   words  = Philox4x32-10(counter = (k >> 2, t, frame lo, frame hi),
+//                          key = (seed lo, seed hi))        [Salmon et al. SC'11]
+//   pair p of the quad uses words (2p, 2p+1) = (a, b):
+//     u1  = ((a >> 8) + 1) * 2^-24          in (0, 1]
+//     phi = 2 pi (b >> 8) 2^-24             in [0, 2 pi)
+//     z   = sqrt(-2 ln u1) * (cos phi, sin phi)
+//   bit 4j + 2p + 0 takes the cosine branch, 4j + 2p + 1 the sine branch.
+//
+// ln, sin and cos are fixed binary32 operation sequences (below); sqrt and
+// the one division are IEEE correctly rounded; every fma is explicit and the
+// file is compiled with -ffp-contract=off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ngdbf {
+
+// Philox-4x32 round multipliers and key (Weyl) increments, as published.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+struct Words4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+// Ten Philox-4x32 rounds.  The key schedule depends only on the seed, so it
+// stays in scalar registers when the key is wave-uniform.
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// binary32 constants, written as exact hex literals
+constexpr float kSqrt2 = 0x1.6a09e6p+0f;      // fl(sqrt 2)
+constexpr float kTwoLn2 = 0x1.62e430p+0f;     // fl(2 ln 2)
+constexpr float kTwoPiM24 = 0x1.921fb6p-22f;  // fl(2 pi) * 2^-24
+// 2 atanh(s) = 2 s (1 + s^2/3 + s^4/5 + ... + s^10/11)
+constexpr float kA3 = 0x1.555556p-2f, kA5 = 0x1.99999ap-3f, kA7 = 0x1.24924ap-3f,
+                kA9 = 0x1.c71c72p-4f, kA11 = 0x1.745d18p-4f;
+// sin a = a + a^3 (-1/3! + a^2 (1/5! + a^2 (-1/7! + a^2 / 9!)))
+constexpr float kS3 = -0x1.555556p-3f, kS5 = 0x1.111112p-7f, kS7 = -0x1.a01a02p-13f,
+                kS9 = 0x1.71de3ap-19f;
+// cos a = 1 + a^2 (-1/2! + a^2 (1/4! + a^2 (-1/6! + a^2 (1/8! - a^2/10!))))
+constexpr float kC2 = -0.5f, kC4 = 0x1.555556p-5f, kC6 = -0x1.6c16c2p-10f,
+                kC8 = 0x1.a01a02p-16f, kC10 = -0x1.27e4fcp-22f;
+
+// Box-Muller radius for u1 = m 2^-24, m in [1, 2^24]:
+// m = f 2^e with f in [1/sqrt2, sqrt2); ln u1 = (e - 24) ln 2 + 2 atanh((f-1)/(f+1)).
+__device__ __forceinline__ float bm_radius(uint32_t m) {
+  int e = 31 - __builtin_clz(m);
+  float f = ldexpf((float)m, -e);
+  if (f > kSqrt2) {
+    f = f * 0.5f;
+    e = e + 1;
+  }
+  const float s = (f - 1.0f) / (f + 1.0f);
+  const float s2 = s * s;
+  float p = __builtin_fmaf(s2, kA11, kA9);
+  p = __builtin_fmaf(s2, p, kA7);
+  p = __builtin_fmaf(s2, p, kA5);
+  p = __builtin_fmaf(s2, p, kA3);
+  p = __builtin_fmaf(s2, p, 1.0f);
+  const float base = (float)(24 - e) * kTwoLn2;
+  return sqrtf(__builtin_fmaf(-4.0f * s, p, base));
+}
+
+// cos and sin of the angle 2 pi i 2^-24, i in [0, 2^24): exact quadrant and
+// octant reduction on the integer, then the series on [0, pi/4].
+__device__ __forceinline__ void bm_turn(uint32_t i, float &co, float &si) {
+  const uint32_t q = (i >> 22) & 3u;
+  const uint32_t r = i & 0x3FFFFFu;
+  const bool refl = r > 0x200000u;
+  const uint32_t rr = refl ? (0x400000u - r) : r;
+  const float a = (float)rr * kTwoPiM24;
+  const float a2 = a * a;
+  float ps = __builtin_fmaf(a2, kS9, kS7);
+  ps = __builtin_fmaf(a2, ps, kS5);
+  ps = __builtin_fmaf(a2, ps, kS3);
+  float sn = __builtin_fmaf(a * a2, ps, a);
+  float pc = __builtin_fmaf(a2, kC10, kC8);
+  pc = __builtin_fmaf(a2, pc, kC6);
+  pc = __builtin_fmaf(a2, pc, kC4);
+  pc = __builtin_fmaf(a2, pc, kC2);
+  float cs = __builtin_fmaf(a2, pc, 1.0f);
+  if (refl) {
+    const float t = sn;
+    sn = cs;
+    cs = t;
+  }
+  // quarter turns: (c, s) -> (-s, c)
+  const bool swap = (q & 1u) != 0;
+  const float c1 = swap ? sn : cs;
+  const float s1 = swap ? cs : sn;
+  co = (q == 1u || q == 2u) ? -c1 : c1;
+  si = (q >= 2u) ? -s1 : s1;
+}
+
+__device__ __forceinline__ void bm_pair(uint32_t a, uint32_t b, float &z0, float &z1) {
+  const float rho = bm_radius((a >> 8) + 1u);
+  float c, s;
+  bm_turn(b >> 8, c, s);
+  z0 = rho * c;
+  z1 = rho * s;
+}
+
+// The four draws of bit quad j (bits 4j .. 4j+3) of a frame at round t.
+struct Draw4 {
+  float z[4];
+};
+
+__device__ __forceinline__ Draw4 draw_quad(uint32_t j, uint32_t t, uint64_t frame,
+                                           uint32_t k0, uint32_t k1) {
+  const Words4 w = philox4x32_10(j, t, (uint32_t)frame, (uint32_t)(frame >> 32), k0, k1);
+  Draw4 d;
+  bm_pair(w.w0, w.w1, d.z[0], d.z[1]);
+  bm_pair(w.w2, w.w3, d.z[2], d.z[3]);
+  return d;
+}
+
+}  // namespace ngdbf

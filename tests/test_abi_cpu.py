@@ -1,0 +1,74 @@
+"""The C ABI library loads, exports every entry point of include/ngdbf.h,
+and rejects invalid arguments on the host (no GPU needed for these paths)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1402_2773_amd as ng
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ng.LIB_PATH):
+        from paper_1402_2773_amd import build
+
+        build.build()
+    return ng.lib()
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "ngdbf.h")) as f:
+        src = f.read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(ngdbf_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_binding_functions():
+    assert sorted(ng.ABI_FUNCTIONS) == _declared()
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_create_code_rejects_bad_tables(L):
+    with pytest.raises(ng.NgdbfError, match="row_ptr"):
+        ng.ngdbf_create_code(4, 2, [1, 2, 4], [0, 1, 2, 3])
+    with pytest.raises(ng.NgdbfError, match="out of range"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 4], [0, 1, 2, 9])
+    with pytest.raises(ng.NgdbfError, match="repeats"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 4], [0, 0, 2, 3])
+    with pytest.raises(ng.NgdbfError, match="empty"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 2], [0, 1])
+    with pytest.raises(ng.NgdbfError, match="column 3 is empty"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 3], [0, 1, 2])
+    with pytest.raises(ng.NgdbfError, match="m < n"):
+        ng.ngdbf_create_code(2, 2, [0, 1, 2], [0, 1])
+
+
+def test_decode_rejects_null_code(L):
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    with pytest.raises(ng.NgdbfError, match="code is NULL"):
+        ng.ngdbf_decode(None, None, 0, None, 0.5, p, 1, 0, None, None, None, 0)
+    assert ng.ngdbf_last_error() == "code is NULL"
+
+
+def test_noise_probe_rejects_bad_ranges(L):
+    buf = np.zeros(4, dtype=np.float32)
+    with pytest.raises(ng.NgdbfError, match="unknown probe kind"):
+        ng.ngdbf_noise_probe(7, 0, 1, 0, 0, 0, buf, None, 0)
+    with pytest.raises(ng.NgdbfError, match="radius probe range"):
+        ng.ngdbf_noise_probe(0, 0, 1, 0, 0, 0, buf, None, 0)
+    with pytest.raises(ng.NgdbfError, match="angle probe range"):
+        ng.ngdbf_noise_probe(1, (1 << 24) - 1, 2, 0, 0, 0, buf, buf, 0)
+
+
+def test_params_struct_layout_matches_header():
+    assert ctypes.sizeof(ng.ngdbf_params) == 32
+    names = [f[0] for f in ng.ngdbf_params._fields_]
+    assert names == ["w", "theta", "lam", "eta", "ymax", "t_max", "smooth_window", "y_format"]
