@@ -3,24 +3,20 @@
 // Data layout.
 //   HBM: y frame-major [F][n] (float32 or int8), sigma [F], outputs
 //        out_bits [F][ceil(n/8)], out_iters [F], out_converged [F].
-//   Code tables (library-owned, uploaded once): one blob of uint16 arrays
-//        row_ptr[m+1] | col_idx[nnz] | col_ptr[n+1] | row_idx[nnz]
-//        i.e. N(i) in CSR and M(k) in CSC (Sec. III-A), staged into LDS once
-//        per workgroup and reused for every frame the workgroup decodes.
-//   LDS per workgroup: the table blob, the decisions x (one byte per bit,
-//        1 = x_k is -1) and the syndrome s (one byte per check, 1 = s_i is -1).
-//   Registers: each lane owns QPL bit quads (bits 4j .. 4j+3, j = lane +
-//        blockDim * r) and keeps their saturated y_k, thresholds theta_k and
-//        smoothing counters X_k; the quad is also the unit of one Philox call.
+//   Code tables (library-owned, int32, read through L1/L2): N(i) as CSR
+//        row_ptr/col_idx and M(k) as CSC col_ptr/row_idx (Sec. III-A).  After
+//        a frame's first syndrome they are only touched for flipped bits.
+//   LDS per frame: syndrome bits s, per-bit counts u_k of unsatisfied checks,
+//        the unsatisfied-check count and an x/flip bit row; per wavefront a
+//        small Box-Muller work list.  A few KB per frame, so occupancy is set
+//        by registers.
+//   Registers: each lane owns QPL bit quads (bits 4j .. 4j+3) and keeps their
+//        saturated y_k, thresholds theta_k, smoothing counters and decisions.
 //
-// One workgroup decodes one frame at a time and loops over frames with a
-// grid stride (persistent grid sized to the resident capacity).  Per round:
-//   phase A  every lane forms the syndromes of its checks from LDS x,
-//            a workgroup OR gives the stop test (Sec. III-B Steps 1, 4);
-//   phase B  every lane forms S_k = sum_{i in M(k)} s_i for its bits from LDS
-//            s, draws its quad's four Gaussians, evaluates E_k and applies
-//            the flip / threshold update (Steps 2, 3b; Sec. III-C, III-D).
-// HBM is touched once per frame (y in, bits out); all rounds run on chip.
+// Frames are independent (Sec. IV): one wavefront decodes a frame of up to
+// 1024 bits with no workgroup barrier in its round loop; longer codes use
+// 2 or 4 wavefronts per frame.  Every round runs on chip; HBM sees y once
+// and the decoded bits once per frame.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,11 +36,23 @@
 
 namespace ngdbf {
 
+constexpr int kWave = 64;
+// Box-Muller work-list entries per wavefront (pairs whose flip decision the
+// radius bound could not settle); past this a lane transforms its own pairs.
+constexpr int kListCap = 256;
+// a list entry: the pair's two Philox words, a_k and theta_k of both bits
+constexpr int kEntryWords = 6;
+// smoothing counters are 16-bit halves biased by this value
+constexpr uint32_t kXBias = 32768u;
+
 struct DecodeArgs {
-  const uint32_t *tables;  // code blob (dwords)
-  int32_t n, m, nnz;
-  int32_t blob_words;      // dwords in the blob
-  int32_t off_col, off_colptr, off_row;  // uint16 offsets (row_ptr at 0)
+  // code tables, uint16, staged into LDS: col_idx (N(i), CSR) | row_idx
+  // (M(k), CSC) | row_ptr | col_ptr (the pointers only for irregular codes)
+  const uint32_t *tables;
+  int32_t table_words;
+  int32_t off_row, off_rowptr, off_colptr;  // uint16 offsets
+  int32_t dv, dc;                           // uniform degrees, 0 if irregular
+  int32_t n, m;
   const void *y;
   int64_t n_frames;
   const float *sigma;
@@ -57,6 +65,9 @@ struct DecodeArgs {
   int32_t *out_iters;
   uint8_t *out_conv;
   uint8_t *trace;
+  int32_t frames_per_block;               // frame slots per workgroup
+  int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
+  int32_t slot_words;                     // LDS words per frame slot
 };
 
 template <int YFMT>
@@ -79,149 +90,340 @@ __device__ __forceinline__ float saturate(float v, float ymax) {
   return v;
 }
 
-template <int QPL, int YFMT, bool TRACE>
-__global__ void __launch_bounds__(1024) decode_kernel(DecodeArgs a) {
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronisation of the waves that share one frame: the wave itself when a
+// single wavefront owns the frame, the workgroup (= the frame) otherwise.
+template <int WPF>
+__device__ __forceinline__ void frame_sync() {
+  if (WPF == 1) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
+}
+
+// number of set bits of a 64-bit wave mask below this lane
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Finish the listed pairs of one wavefront: lanes take entries in turn, draw
+// the pair's two Gaussians, and decide E_k = fmaf(qs, z_k, a_k) < theta_k for
+// both bits; each owner then reads its two decision bits back.
+__device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t total, float qs,
+                                           uint32_t pend, uint64_t posb, uint32_t &flip) {
+  wave_sync();
+  for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+    uint32_t *ent = list + kEntryWords * e;
+    float z0, z1;
+    bm_pair(ent[0], ent[1], z0, z1);
+    const float E0 = __builtin_fmaf(qs, z0, __uint_as_float(ent[2]));
+    const float E1 = __builtin_fmaf(qs, z1, __uint_as_float(ent[3]));
+    ent[0] = (E0 < __uint_as_float(ent[4]) ? 1u : 0u) | (E1 < __uint_as_float(ent[5]) ? 2u : 0u);
+  }
+  wave_sync();
+  while (pend) {
+    const int q2 = __builtin_ctz(pend);
+    pend &= pend - 1;
+    const uint32_t ps = (uint32_t)(posb >> (8 * q2)) & 255u;
+    const uint32_t bits = list[kEntryWords * ps];
+    flip = (flip & ~(3u << (2 * q2))) | (bits << (2 * q2));
+  }
+  wave_sync();  // the list is refilled next
+}
+
+// Edges of check i (N(i)) and of bit k (M(k)) in the LDS tables.
+struct Tables {
+  const uint16_t *col_idx, *row_idx, *row_ptr, *col_ptr;
+  int dv, dc;
+  __device__ __forceinline__ int row_begin(int i) const { return dc ? i * dc : row_ptr[i]; }
+  __device__ __forceinline__ int row_end(int i) const { return dc ? i * dc + dc : row_ptr[i + 1]; }
+  __device__ __forceinline__ int col_begin(int k) const { return dv ? k * dv : col_ptr[k]; }
+  __device__ __forceinline__ int col_end(int k) const { return dv ? k * dv + dv : col_ptr[k + 1]; }
+};
+
+// Decode kernel.  WPF wavefronts cooperate on one frame; each lane owns QPL
+// bit quads j = ft + 64*WPF*r (ft = lane index within the frame).  With
+// WPF == 1 a workgroup holds several independent frames, one per wave, and
+// the round loop has no workgroup barrier.
+//
+// Per frame in LDS: s (one bit per check, 1 = unsatisfied), u_k (one byte per
+// bit: number of unsatisfied checks among M(k)), the count of unsatisfied
+// checks, and an x / flip bit row.  Per wave: the Box-Muller list.
+//
+// Round t (Sec. III-B/C/D):
+//   stop test on the unsatisfied count;
+//   for every owned bit S_k = deg_k - 2 u_k and a_k = fmaf(w, S_k, x_k y_k);
+//   one Philox call per quad; a pair of bits whose decision the bound on the
+//   Box-Muller radius settles (below) needs no transform; the others are
+//   compacted into the wave's list, transformed densely, and finished by
+//   their owners with E_k = fmaf(qs, z_k, a_k) < theta_k;
+//   each flip toggles s_i of its checks with LDS atomics, and each toggle
+//   moves u of the check's bits and the unsatisfied count by +-1.
+//
+// Exactness of the bound.  With m = (a >> 8) + 1 = f 2^e, u1 >= 2^(e-24), so
+// the radius is at most sqrt(2 (24 - e) ln 2) (the computed radius exceeds it
+// by less than 1e-7 relative), and |z| <= radius since |cos|, |sin| <= 1.
+// If a_k - theta_k >= qs * bound, every draw gives E_k >= theta_k (fma
+// rounding is monotone and theta_k is a float): no flip, and the pair needs
+// no transform.  The test runs on squares with a 4e-5 relative slack that
+// covers all rounding.  Every other pair goes through the transform.
+template <int WPF, int QPL, int YFMT, bool TRACE, bool REG>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+decode_kernel(DecodeArgs a) {
   extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
-  const int B = blockDim.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int fslot = wave / WPF;                // frame slot within the workgroup
+  const int ft = tid - fslot * WPF * kWave;    // lane index within the frame
+  constexpr int FT = WPF * kWave;              // lanes per frame
   const int n = a.n, m = a.m;
   const int nq = (n + 3) >> 2;
   const int nbytes = (n + 7) >> 3;
   const int T = a.t_max, W = a.smooth_window;
 
   // stage the code tables once per workgroup
-  for (int i = tid; i < a.blob_words; i += B) lds[i] = a.tables[i];
+  for (int i = tid; i < a.table_words; i += blockDim.x) lds[i] = a.tables[i];
   const uint16_t *t16 = (const uint16_t *)lds;
-  const uint16_t *row_ptr = t16;
-  const uint16_t *col_idx = t16 + a.off_col;
-  const uint16_t *col_ptr = t16 + a.off_colptr;
-  const uint16_t *row_idx = t16 + a.off_row;
-  uint8_t *xb = (uint8_t *)(lds + a.blob_words);          // [n]  1 = x_k is -1
-  uint8_t *sb = xb + ((n + 3) & ~3);                        // [m]  1 = s_i is -1
-  uint8_t *fb = sb + ((m + 3) & ~3);                        // [n]  flips (trace)
+  Tables tab;
+  tab.col_idx = t16;
+  tab.row_idx = t16 + a.off_row;
+  tab.row_ptr = t16 + a.off_rowptr;
+  tab.col_ptr = t16 + a.off_colptr;
+  tab.dv = a.dv;
+  tab.dc = a.dc;
+  uint32_t *slot = lds + a.table_words + fslot * a.slot_words;
+  uint32_t *sw = slot;                     // [sw_words] syndrome bits
+  uint32_t *uw = sw + a.sw_words;          // [uw_words] u_k bytes
+  uint32_t *xw = uw + a.uw_words;          // [xw_words] x / output bits
+  uint32_t *fw = xw + a.xw_words;          // [xw_words] flip bits (trace)
+  uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
+  uint32_t *list = lds + a.table_words + a.frames_per_block * a.slot_words + wave * (kEntryWords * kListCap);
   __syncthreads();
 
-  for (int64_t f = blockIdx.x; f < a.n_frames; f += gridDim.x) {
+  const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
+  for (int64_t f = (int64_t)blockIdx.x * a.frames_per_block + fslot; f < a.n_frames;
+       f += slots_total) {
     const uint64_t frame = a.frame_base + (uint64_t)f;
     const float sigma_f = a.sigma ? a.sigma[f] : a.sigma_scalar;
     const float qs = a.eta * sigma_f;  // perturbation std (Sec. III-C)
+    // qs^2 * 2 ln 2 with a relative slack of 4e-5 (radius bound, squared)
+    const float bound_c = (qs * qs) * 0x1.62e8p+0f;
 
-    // Step 0 and x(0) = sign(y): -1 iff the saturated sample is < 0
+    for (int i = ft; i < a.slot_words; i += FT) slot[i] = 0u;
+    frame_sync<WPF>();
+
+    // Step 0, x(0) = sign(y) with y saturated (Sec. III-A, IV-A)
     float yv[QPL * 4], thr[QPL * 4];
-    int X[QPL * 4];
-    uint32_t xneg = 0;  // bit 4r+b: x of bit 4(tid+B r)+b is -1
+    uint32_t X2[QPL * 2];  // smoothing sums, two biased 16-bit halves each
+    uint32_t deg4[QPL];    // column degrees, one nibble per bit (irregular codes)
+    uint32_t xneg = 0;     // bit 4r+b: x_k = -1 for k = 4 j_r + b
 #pragma unroll
     for (int r = 0; r < QPL; ++r) {
-      const int j = tid + B * r;
+      const int j = ft + FT * r;
+      uint32_t nib = 0, dg = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int k = 4 * j + b;
         float v = 0.0f;
-        if (j < nq && k < n) v = saturate(load_sample<YFMT>(a.y, f * (int64_t)n + k), a.ymax);
+        if (j < nq && k < n) {
+          v = saturate(load_sample<YFMT>(a.y, f * (int64_t)n + k), a.ymax);
+          if (!REG) dg |= (uint32_t)(tab.col_ptr[k + 1] - tab.col_ptr[k]) << (4 * b);
+        }
         yv[4 * r + b] = v;
         thr[4 * r + b] = a.theta;
-        X[4 * r + b] = 0;
-        const uint32_t neg = (v < 0.0f) ? 1u : 0u;
-        xneg |= neg << (4 * r + b);
-        if (j < nq && k < n) xb[k] = (uint8_t)neg;
+        nib |= (v < 0.0f ? 1u : 0u) << b;
+      }
+      X2[2 * r] = X2[2 * r + 1] = (kXBias << 16) | kXBias;
+      deg4[r] = dg;
+      xneg |= nib << (4 * r);
+      if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
+    }
+    frame_sync<WPF>();
+
+    // s(0), u(0) and the unsatisfied count from x(0)
+    uint32_t nunsat = 0;
+    for (int i = ft; i < m; i += FT) {
+      const int e0 = tab.row_begin(i), e1 = tab.row_end(i);
+      uint32_t v = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int k = tab.col_idx[e];
+        v ^= (xw[k >> 5] >> (k & 31)) & 1u;
+      }
+      if (v) {
+        atomicOr(&sw[i >> 5], 1u << (i & 31));
+        ++nunsat;
+        for (int e = e0; e < e1; ++e) {
+          const int k = tab.col_idx[e];
+          atomicAdd(&uw[k >> 2], 1u << (8 * (k & 3)));
+        }
       }
     }
-    __syncthreads();
+    if (nunsat) atomicAdd(cnt, nunsat);
+    frame_sync<WPF>();
 
     int t = 0;
     int converged = 0;
     for (;; ++t) {
-      // phase A: s_i = prod_{j in N(i)} x_j  (XOR of the -1 flags)
-      int unsat = 0;
-      for (int i = tid; i < m; i += B) {
-        uint32_t v = 0;
-        const int e1 = row_ptr[i + 1];
-        for (int e = row_ptr[i]; e < e1; ++e) v ^= xb[col_idx[e]];
-        sb[i] = (uint8_t)v;
-        unsat |= (int)v;
-      }
+      const uint32_t unsat = *(volatile uint32_t *)cnt;
       // smoothing window t = T-W .. T (Sec. III-E)
       if (W > 0 && t >= T - W) {
 #pragma unroll
-        for (int q = 0; q < QPL * 4; ++q) X[q] += ((xneg >> q) & 1u) ? -1 : 1;
+        for (int q = 0; q < QPL * 4; ++q)
+          X2[q >> 1] += (((xneg >> q) & 1u) ? 0xFFFFFFFFu : 1u) << (16 * (q & 1));
       }
-      unsat = __syncthreads_or(unsat);
-      if (!unsat) {
+      if (unsat == 0) {
         converged = 1;
         break;
       }
       if (t == T) break;
 
-      // phase B: E_k and the flip / adaptation of every owned bit
+      // ---- decisions for every owned bit (Steps 2, 3b)
+      uint32_t flip = 0;     // bit 4r+b: flip in this round
+      uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
+      uint64_t posb = 0;     // list slot of each waiting pair, one byte each
+      uint32_t total = 0;    // wave-uniform list length
 #pragma unroll
       for (int r = 0; r < QPL; ++r) {
-        const int j = tid + B * r;
-        if (j < nq) {
-          const Draw4 d = draw_quad((uint32_t)j, (uint32_t)t, frame, a.key0, a.key1);
+        // a quad adds at most 2 * 64 entries: drain the list first if needed
+        if (r > 0 && total > (uint32_t)(kListCap - 2 * kWave)) {
+          flush_list(list, lane, total, qs, pend, posb, flip);
+          total = 0;
+          pend = 0;
+          posb = 0;
+        }
+        const int j = ft + FT * r;
+        const bool valid = j < nq;
+        Words4 wd = {0u, 0u, 0u, 0u};
+        uint32_t u4 = 0;
+        if (valid) {
+          wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame, (uint32_t)(frame >> 32),
+                             a.key0, a.key1);
+          u4 = uw[j];
+        }
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int k = 4 * j + b;
+        for (int p = 0; p < 2; ++p) {
+          const uint32_t wa = p ? wd.w2 : wd.w0;
+          const uint32_t wb = p ? wd.w3 : wd.w1;
+          const int e = 31 - __builtin_clz((wa >> 8) + 1u);
+          const float lim = (float)(24 - e) * bound_c;
+          bool settled = true;
+          float avh[2], thh[2];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int b = 2 * p + h;
             const int q = 4 * r + b;
-            if (k < n) {
-              int S = 0;
-              const int e1 = col_ptr[k + 1];
-              for (int e = col_ptr[k]; e < e1; ++e) S += sb[row_idx[e]] ? -1 : 1;
-              const float xk = ((xneg >> q) & 1u) ? -1.0f : 1.0f;
-              const float av = __builtin_fmaf(a.w, (float)S, xk * yv[q]);
-              const float E = __builtin_fmaf(qs, d.z[b], av);
-              const bool flip = E < thr[q];
-              if (flip) {
-                xneg ^= 1u << q;
-                xb[k] = (uint8_t)((xneg >> q) & 1u);
-              } else {
-                thr[q] = thr[q] * a.lambda;
-              }
-              if (TRACE) fb[k] = flip ? 1 : 0;
-            }
+            const int deg = REG ? a.dv : (int)((deg4[r] >> (4 * b)) & 15u);
+            const int S = deg - 2 * (int)((u4 >> (8 * b)) & 255u);
+            const float xk = ((xneg >> q) & 1u) ? -1.0f : 1.0f;
+            const float av = __builtin_fmaf(a.w, (float)S, xk * yv[q]);
+            const float mg = av - thr[q];
+            const bool real = valid && 4 * j + b < n;
+            avh[h] = av;
+            thh[h] = real ? thr[q] : -INFINITY;  // a bit past n never flips
+            // settled without a draw: a_k - theta_k >= qs * bound (no flip)
+            if (real && !(mg >= 0.0f && mg * mg >= lim)) settled = false;
+          }
+          const uint64_t bal = __ballot(!settled);
+          if (!settled) {
+            const uint32_t ps = total + mask_rank(bal);
+            const int q2 = 2 * r + p;
+            pend |= 1u << q2;
+            posb |= (uint64_t)ps << (8 * q2);
+            uint32_t *ent = list + kEntryWords * ps;
+            ent[0] = wa;
+            ent[1] = wb;
+            ent[2] = __float_as_uint(avh[0]);
+            ent[3] = __float_as_uint(avh[1]);
+            ent[4] = __float_as_uint(thh[0]);
+            ent[5] = __float_as_uint(thh[1]);
+          }
+          total += (uint32_t)__popcll(bal);
+        }
+      }
+      if (total) flush_list(list, lane, total, qs, pend, posb, flip);
+
+      // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
+#pragma unroll
+      for (int q = 0; q < QPL * 4; ++q)
+        if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
+      xneg ^= flip;
+      if (TRACE) {
+#pragma unroll
+        for (int r = 0; r < QPL; ++r) {
+          const int j = ft + FT * r;
+          const uint32_t nib = (flip >> (4 * r)) & 15u;
+          if (j < nq && nib) atomicOr(&fw[j >> 3], nib << (4 * (j & 7)));
+        }
+      }
+      frame_sync<WPF>();  // every wave has read u before any toggle lands
+      uint32_t fl = flip;
+      int32_t dcnt = 0;
+      while (fl) {
+        const int q = __builtin_ctz(fl);
+        fl &= fl - 1;
+        const int k = 4 * (ft + FT * (q >> 2)) + (q & 3);
+        const int c0 = REG ? k * a.dv : tab.col_ptr[k];
+        const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
+        for (int e = c0; e < c1; ++e) {
+          const int i = tab.row_idx[e];
+          const uint32_t old = atomicXor(&sw[i >> 5], 1u << (i & 31));
+          const bool became_unsat = ((old >> (i & 31)) & 1u) == 0u;
+          const uint32_t d = became_unsat ? 1u : 0xFFFFFFFFu;  // +1 / -1
+          dcnt += became_unsat ? 1 : -1;
+          const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
+#pragma unroll 4
+          for (int e2 = r0; e2 < r1; ++e2) {
+            const int k2 = tab.col_idx[e2];
+            atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
           }
         }
       }
-      __syncthreads();
+      if (dcnt) atomicAdd(cnt, (uint32_t)dcnt);
+      frame_sync<WPF>();
       if (TRACE) {
         uint8_t *row = a.trace + ((size_t)f * (size_t)T + (size_t)t) * (size_t)nbytes;
-        for (int bb = tid; bb < nbytes; bb += B) {
-          uint32_t v = 0;
-          for (int i = 0; i < 8; ++i) {
-            const int k = 8 * bb + i;
-            if (k < n) v |= (uint32_t)fb[k] << i;
-          }
-          row[bb] = (uint8_t)v;
-        }
+        const uint8_t *fb = (const uint8_t *)fw;
+        for (int bb = ft; bb < nbytes; bb += FT) row[bb] = fb[bb];
+        frame_sync<WPF>();
+        for (int i = ft; i < a.xw_words; i += FT) fw[i] = 0u;
+        frame_sync<WPF>();
       }
     }
 
-    // output: x, or sign(X) when T was reached with smoothing on
-    if (!converged && W > 0) {
+    // output: x, or sign(X) when T was reached with smoothing on (Sec. III-E)
+    for (int i = ft; i < a.xw_words; i += FT) xw[i] = 0u;
+    frame_sync<WPF>();
 #pragma unroll
-      for (int r = 0; r < QPL; ++r) {
-        const int j = tid + B * r;
+    for (int r = 0; r < QPL; ++r) {
+      const int j = ft + FT * r;
+      uint32_t nib = (xneg >> (4 * r)) & 15u;
+      if (!converged && W > 0) {
+        nib = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int k = 4 * j + b;
-          if (j < nq && k < n) xb[k] = (uint8_t)(X[4 * r + b] < 0 ? 1 : 0);
+          const uint32_t half = (X2[2 * r + (b >> 1)] >> (16 * (b & 1))) & 0xFFFFu;
+          nib |= (half < kXBias ? 1u : 0u) << b;
         }
       }
+      if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
     }
-    __syncthreads();
+    frame_sync<WPF>();
     uint8_t *ob = a.out_bits + (size_t)f * (size_t)nbytes;
-    for (int bb = tid; bb < nbytes; bb += B) {
-      uint32_t v = 0;
-      for (int i = 0; i < 8; ++i) {
-        const int k = 8 * bb + i;
-        if (k < n) v |= (uint32_t)xb[k] << i;
-      }
-      ob[bb] = (uint8_t)v;
-    }
-    if (tid == 0) {
+    const uint8_t *xb = (const uint8_t *)xw;
+    for (int bb = ft; bb < nbytes; bb += FT) ob[bb] = xb[bb];
+    if (ft == 0) {
       a.out_iters[f] = t;
       if (a.out_conv) a.out_conv[f] = (uint8_t)converged;
     }
-    __syncthreads();  // xb is rewritten by the next frame
+    frame_sync<WPF>();  // the slot is cleared for the next frame
   }
 }
 
@@ -258,9 +460,10 @@ __global__ void probe_quad_kernel(uint32_t start, uint32_t count, uint64_t frame
 struct ngdbf_code {
   int32_t n, m, nnz;
   int device;
-  uint32_t *d_blob;
-  int32_t blob_words;
-  int32_t off_col, off_colptr, off_row;
+  uint32_t *d_tables;  // uint16 col_idx | row_idx [| row_ptr | col_ptr], dword padded
+  int32_t table_words;
+  int32_t off_row, off_rowptr, off_colptr;
+  int32_t dv, dc;      // uniform degrees (0 if irregular)
   int32_t max_col_deg, max_row_deg;
 };
 
@@ -284,7 +487,6 @@ int ok() {
 
 struct DeviceInfo {
   int cus = 0;
-  size_t lds_max = 0;
 };
 
 DeviceInfo device_info(int dev) {
@@ -294,45 +496,69 @@ DeviceInfo device_info(int dev) {
   if ((int)cache.size() <= dev) cache.resize(dev + 1);
   if (cache[dev].cus == 0) {
     hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) == hipSuccess) {
-      cache[dev].cus = p.multiProcessorCount;
-      cache[dev].lds_max = p.sharedMemPerBlock;
-    }
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cache[dev].cus = p.multiProcessorCount;
   }
   return cache[dev];
 }
 
-template <int QPL, int YFMT, bool TRACE>
-int launch(const ngdbf::DecodeArgs &a, int block, size_t lds_bytes, int dev, hipStream_t s) {
-  auto kern = ngdbf::decode_kernel<QPL, YFMT, TRACE>;
-  if (lds_bytes > 64 * 1024) {
-    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes) != hipSuccess)
-      return fail(NGDBF_EDEVICE, "cannot raise the LDS limit to %zu bytes", lds_bytes);
+// Launch shape for a code: WPF waves per frame, QPL quads per lane.
+struct Shape {
+  int wpf, qpl, block, fpb;
+};
+
+int choose_shape(int n, Shape *s) {
+  const int nq = (n + 3) / 4;
+  for (int wpf : {1, 2, 4}) {
+    for (int qpl : {1, 2, 4}) {
+      if (nq <= wpf * 64 * qpl) {
+        // one frame per wave, four per workgroup; a frame spanning several
+        // waves is a workgroup of its own (its barriers are per frame)
+        s->wpf = wpf;
+        s->qpl = qpl;
+        s->fpb = wpf == 1 ? 8 : 1;
+        s->block = wpf == 1 ? 512 : 64 * wpf;
+        return NGDBF_OK;
+      }
+    }
   }
+  return fail(NGDBF_EUNSUPPORTED, "n = %d exceeds the 4096 bits one workgroup decodes", n);
+}
+
+template <int WPF, int QPL, int YFMT, bool TRACE, bool REG>
+int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int dev, hipStream_t s) {
+  auto kern = ngdbf::decode_kernel<WPF, QPL, YFMT, TRACE, REG>;
+  if (lds_bytes > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes) != hipSuccess)
+    return fail(NGDBF_EUNSUPPORTED, "cannot raise the LDS limit to %zu bytes", lds_bytes);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds_bytes) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, sh.block, lds_bytes) != hipSuccess ||
       per_cu <= 0)
     return fail(NGDBF_EUNSUPPORTED, "kernel does not fit a compute unit (block %d, LDS %zu B)",
-                block, lds_bytes);
+                sh.block, lds_bytes);
   const DeviceInfo di = device_info(dev);
+  const int64_t blocks_needed = (a.n_frames + sh.fpb - 1) / sh.fpb;
   int64_t grid = (int64_t)per_cu * std::max(di.cus, 1);
-  grid = std::min<int64_t>(grid, a.n_frames);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds_bytes, s, a);
+  grid = std::min<int64_t>(grid, blocks_needed);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.block), lds_bytes, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
 }
 
 template <int YFMT, bool TRACE>
-int dispatch_qpl(int qpl, const ngdbf::DecodeArgs &a, int block, size_t lds, int dev,
-                 hipStream_t s) {
-  switch (qpl) {
-    case 1: return launch<1, YFMT, TRACE>(a, block, lds, dev, s);
-    case 2: return launch<2, YFMT, TRACE>(a, block, lds, dev, s);
-    case 4: return launch<4, YFMT, TRACE>(a, block, lds, dev, s);
-    default: return fail(NGDBF_EUNSUPPORTED, "no kernel for %d quads per lane", qpl);
-  }
+int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, hipStream_t s) {
+#define NGDBF_CASE(W_, Q_)                                                         \
+  if (sh.wpf == W_ && sh.qpl == Q_)                                                \
+    return a.dv ? launch<W_, Q_, YFMT, TRACE, true>(a, sh, lds, dev, s)            \
+                : launch<W_, Q_, YFMT, TRACE, false>(a, sh, lds, dev, s);
+  NGDBF_CASE(1, 1)
+  NGDBF_CASE(1, 2)
+  NGDBF_CASE(1, 4)
+  NGDBF_CASE(2, 4)
+  NGDBF_CASE(4, 4)
+#undef NGDBF_CASE
+  return fail(NGDBF_EUNSUPPORTED, "no kernel for %d waves x %d quads", sh.wpf, sh.qpl);
 }
 
 int check_params(const ngdbf_params *p) {
@@ -380,15 +606,21 @@ int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const
   }
   if (n_frames == 0) return ok();
 
+  Shape sh;
+  rc = choose_shape(n, &sh);
+  if (rc) return rc;
+  if (p->smooth_window > 0 && std::min(p->smooth_window, p->t_max) >= 32767)
+    return fail(NGDBF_EUNSUPPORTED, "smoothing over more than 32767 rounds");
   ngdbf::DecodeArgs a;
-  a.tables = code->d_blob;
+  a.tables = code->d_tables;
+  a.table_words = code->table_words;
+  a.off_row = code->off_row;
+  a.off_rowptr = code->off_rowptr;
+  a.off_colptr = code->off_colptr;
+  a.dv = code->dv;
+  a.dc = code->dc;
   a.n = n;
   a.m = m;
-  a.nnz = code->nnz;
-  a.blob_words = code->blob_words;
-  a.off_col = code->off_col;
-  a.off_colptr = code->off_colptr;
-  a.off_row = code->off_row;
   a.y = y;
   a.n_frames = n_frames;
   a.sigma = sigma;
@@ -407,24 +639,20 @@ int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const
   a.out_iters = out_iters;
   a.out_conv = out_conv;
   a.trace = trace;
-
-  // one lane per bit quad where possible: block = next power of two >= quads
-  const int nq = (n + 3) / 4;
-  int block = 64;
-  while (block < nq && block < 1024) block *= 2;
-  int qpl = (nq + block - 1) / block;
-  if (qpl == 3) qpl = 4;
-  const size_t lds = (size_t)code->blob_words * 4 + (size_t)((n + 3) & ~3) +
-                     (size_t)((m + 3) & ~3) + (size_t)((n + 3) & ~3);
-  const DeviceInfo di = device_info(dev);
-  if (di.lds_max && lds > 160 * 1024)
-    return fail(NGDBF_EUNSUPPORTED, "code needs %zu B of LDS", lds);
+  a.frames_per_block = sh.fpb;
+  a.sw_words = (m + 31) / 32;
+  a.uw_words = (n + 3) / 4;
+  a.xw_words = (n + 31) / 32;
+  a.slot_words = a.sw_words + a.uw_words + a.xw_words * (trace ? 2 : 1) + 1;
+  const size_t lds = ((size_t)a.table_words + (size_t)sh.fpb * a.slot_words +
+                      (size_t)(sh.block / 64) * ngdbf::kEntryWords * ngdbf::kListCap) * 4;
+  if (lds > 160 * 1024) return fail(NGDBF_EUNSUPPORTED, "code needs %zu B of LDS", lds);
   if (p->y_format == NGDBF_Y_I8) {
-    return trace ? dispatch_qpl<NGDBF_Y_I8, true>(qpl, a, block, lds, dev, s)
-                 : dispatch_qpl<NGDBF_Y_I8, false>(qpl, a, block, lds, dev, s);
+    return trace ? dispatch<NGDBF_Y_I8, true>(sh, a, lds, dev, s)
+                 : dispatch<NGDBF_Y_I8, false>(sh, a, lds, dev, s);
   }
-  return trace ? dispatch_qpl<NGDBF_Y_F32, true>(qpl, a, block, lds, dev, s)
-               : dispatch_qpl<NGDBF_Y_F32, false>(qpl, a, block, lds, dev, s);
+  return trace ? dispatch<NGDBF_Y_F32, true>(sh, a, lds, dev, s)
+               : dispatch<NGDBF_Y_F32, false>(sh, a, lds, dev, s);
 }
 
 }  // namespace
@@ -444,7 +672,7 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
     if (row_ptr[i + 1] <= row_ptr[i]) return fail(NGDBF_EINVAL, "row %d is empty or row_ptr decreases", i);
   }
   const int64_t nnz = row_ptr[m];
-  if (nnz > 65535) return fail(NGDBF_EUNSUPPORTED, "nnz %lld exceeds 65535", (long long)nnz);
+  if (nnz > (1 << 24)) return fail(NGDBF_EUNSUPPORTED, "nnz %lld exceeds 2^24", (long long)nnz);
   std::vector<int32_t> colcnt(n + 1, 0);
   for (int i = 0; i < m; ++i) {
     for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -463,20 +691,34 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   for (int i = 0; i < m; ++i)
     for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) rowidx[fill[col_idx[e]]++] = i;
 
-  // blob of uint16: row_ptr[m+1] | col_idx[nnz] | col_ptr[n+1] | row_idx[nnz]
-  const int off_col = m + 1;
-  const int off_colptr = off_col + (int)nnz;
-  const int off_row = off_colptr + n + 1;
-  const int total16 = off_row + (int)nnz;
-  const int words = (total16 + 1) / 2;
-  std::vector<uint16_t> blob((size_t)words * 2, 0);
-  int maxr = 0, maxc = 0;
-  for (int i = 0; i <= m; ++i) blob[i] = (uint16_t)row_ptr[i];
-  for (int64_t e = 0; e < nnz; ++e) blob[off_col + e] = (uint16_t)col_idx[e];
-  for (int k = 0; k <= n; ++k) blob[off_colptr + k] = (uint16_t)colptr[k];
-  for (int64_t e = 0; e < nnz; ++e) blob[off_row + e] = (uint16_t)rowidx[e];
-  for (int i = 0; i < m; ++i) maxr = std::max(maxr, row_ptr[i + 1] - row_ptr[i]);
-  for (int k = 0; k < n; ++k) maxc = std::max(maxc, colptr[k + 1] - colptr[k]);
+  int maxr = 0, maxc = 0, minr = 1 << 30, minc = 1 << 30;
+  for (int i = 0; i < m; ++i) {
+    maxr = std::max(maxr, row_ptr[i + 1] - row_ptr[i]);
+    minr = std::min(minr, row_ptr[i + 1] - row_ptr[i]);
+  }
+  for (int k = 0; k < n; ++k) {
+    maxc = std::max(maxc, colptr[k + 1] - colptr[k]);
+    minc = std::min(minc, colptr[k + 1] - colptr[k]);
+  }
+  if (maxc > 15) return fail(NGDBF_EUNSUPPORTED, "column degree %d exceeds 15", maxc);
+  const bool regular = (maxr == minr) && (maxc == minc);
+  if (nnz > 65535 && !regular)
+    return fail(NGDBF_EUNSUPPORTED, "an irregular code needs nnz <= 65535 (16-bit pointers)");
+  // uint16 tables: col_idx | row_idx [| row_ptr | col_ptr]
+  std::vector<uint16_t> t16;
+  t16.reserve((size_t)(2 * nnz + m + n + 4));
+  for (int64_t e = 0; e < nnz; ++e) t16.push_back((uint16_t)col_idx[e]);
+  const int off_row = (int)t16.size();
+  for (int64_t e = 0; e < nnz; ++e) t16.push_back((uint16_t)rowidx[e]);
+  int off_rowptr = 0, off_colptr = 0;
+  if (!regular) {
+    off_rowptr = (int)t16.size();
+    for (int i = 0; i <= m; ++i) t16.push_back((uint16_t)row_ptr[i]);
+    off_colptr = (int)t16.size();
+    for (int k = 0; k <= n; ++k) t16.push_back((uint16_t)colptr[k]);
+  }
+  if (t16.size() & 1) t16.push_back(0);
+  const int words = (int)(t16.size() / 2);
 
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NGDBF_EDEVICE, "no HIP device");
@@ -486,18 +728,21 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   c->m = m;
   c->nnz = (int32_t)nnz;
   c->device = dev;
-  c->blob_words = words;
-  c->off_col = off_col;
-  c->off_colptr = off_colptr;
+  c->table_words = words;
   c->off_row = off_row;
+  c->off_rowptr = off_rowptr;
+  c->off_colptr = off_colptr;
+  c->dv = regular ? maxc : 0;
+  c->dc = regular ? maxr : 0;
   c->max_row_deg = maxr;
   c->max_col_deg = maxc;
-  if (hipMalloc((void **)&c->d_blob, (size_t)words * 4) != hipSuccess) {
+  const size_t bytes = (size_t)words * 4;
+  if (hipMalloc((void **)&c->d_tables, bytes) != hipSuccess) {
     free(c);
-    return fail(NGDBF_ENOMEM, "device allocation of %d words failed", words);
+    return fail(NGDBF_ENOMEM, "device allocation of %zu bytes failed", bytes);
   }
-  if (hipMemcpy(c->d_blob, blob.data(), (size_t)words * 4, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(c->d_blob);
+  if (hipMemcpy(c->d_tables, t16.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c->d_tables);
     free(c);
     return fail(NGDBF_EDEVICE, "upload of the code tables failed");
   }
@@ -507,7 +752,7 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
 
 int ngdbf_destroy_code(ngdbf_code *code) {
   if (!code) return ok();
-  const hipError_t e = hipFree(code->d_blob);
+  const hipError_t e = hipFree(code->d_tables);
   free(code);
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "hipFree failed: %s", hipGetErrorString(e));
   return ok();

@@ -32,6 +32,14 @@ struct Words4 {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ k in one VALU instruction: gfx950's three-input bitwise operation
+// with truth table 0x96 (odd parity); k is wave-uniform (a scalar operand)
+__device__ __forceinline__ uint32_t xor3_sk(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
 // Ten Philox-4x32 rounds.  The key schedule depends only on the seed, so it
 // stays in scalar registers when the key is wave-uniform.
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
@@ -40,8 +48,8 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
     const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3_sk((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_sk((uint32_t)(p0 >> 32), c3, k1);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
