@@ -214,8 +214,10 @@ decode_kernel(DecodeArgs a) {
     const uint64_t frame = a.frame_base + (uint64_t)f;
     const float sigma_f = a.sigma ? a.sigma[f] : a.sigma_scalar;
     const float qs = a.eta * sigma_f;  // perturbation std (Sec. III-C)
-    // qs^2 * 2 ln 2 with a relative slack of 4e-5 (radius bound, squared)
-    const float bound_c = (qs * qs) * 0x1.62e8p+0f;
+    // qs^2 * 2 ln 2 with a relative slack of 4e-5 (radius bound, squared),
+    // floored at 2^-100 so that the settle test below stays strict: a margin
+    // whose square underflows is never taken as settled
+    const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
 
     for (int i = ft; i < a.slot_words; i += FT) slot[i] = 0u;
     frame_sync<WPF>();
@@ -238,7 +240,9 @@ decode_kernel(DecodeArgs a) {
           if (!REG) dg |= (uint32_t)(tab.col_ptr[k + 1] - tab.col_ptr[k]) << (4 * b);
         }
         yv[4 * r + b] = v;
-        thr[4 * r + b] = a.theta;
+        // a bit past n gets theta = -inf: its margin is +inf, so it is settled
+        // every round, never flips and never reaches the output
+        thr[4 * r + b] = (j < nq && k < n) ? a.theta : -INFINITY;
         nib |= (v < 0.0f ? 1u : 0u) << b;
       }
       X2[2 * r] = X2[2 * r + 1] = (kXBias << 16) | kXBias;
@@ -300,36 +304,35 @@ decode_kernel(DecodeArgs a) {
           posb = 0;
         }
         const int j = ft + FT * r;
-        const bool valid = j < nq;
-        Words4 wd = {0u, 0u, 0u, 0u};
-        uint32_t u4 = 0;
-        if (valid) {
-          wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame, (uint32_t)(frame >> 32),
-                             a.key0, a.key1);
-          u4 = uw[j];
-        }
+        // lanes past the last quad run the same code on a clamped index;
+        // their thresholds are -inf, so nothing of theirs is ever listed
+        const int jc = j < nq ? j : nq - 1;
+        const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
+                                        (uint32_t)(frame >> 32), a.key0, a.key1);
+        const uint32_t u4 = uw[jc];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const uint32_t wa = p ? wd.w2 : wd.w0;
           const uint32_t wb = p ? wd.w3 : wd.w1;
-          const int e = 31 - __builtin_clz((wa >> 8) + 1u);
-          const float lim = (float)(24 - e) * bound_c;
+          // m = (wa >> 8) + 1 = f 2^e.  clz(wa | 1) + 1 >= 24 - e (equal unless
+          // wa >> 8 is 2^i - 1 or wa < 256), so the bound is never smaller
+          const float lim = __builtin_fmaf((float)__builtin_clz(wa | 1u), bound_c, bound_c);
+          float avh[2];
           bool settled = true;
-          float avh[2], thh[2];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int b = 2 * p + h;
             const int q = 4 * r + b;
             const int deg = REG ? a.dv : (int)((deg4[r] >> (4 * b)) & 15u);
             const int S = deg - 2 * (int)((u4 >> (8 * b)) & 255u);
-            const float xk = ((xneg >> q) & 1u) ? -1.0f : 1.0f;
-            const float av = __builtin_fmaf(a.w, (float)S, xk * yv[q]);
+            // x_k y_k: flip the sign bit of y_k when x_k = -1 (exact)
+            const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
+            const float av = __builtin_fmaf(a.w, (float)S, xy);
             const float mg = av - thr[q];
-            const bool real = valid && 4 * j + b < n;
             avh[h] = av;
-            thh[h] = real ? thr[q] : -INFINITY;  // a bit past n never flips
-            // settled without a draw: a_k - theta_k >= qs * bound (no flip)
-            if (real && !(mg >= 0.0f && mg * mg >= lim)) settled = false;
+            // settled without a draw: a_k - theta_k >= qs * bound (no flip);
+            // with lim > 0, mg |mg| >= lim implies mg > 0 (NaN fails the test)
+            settled = settled && (mg * fabsf(mg) >= lim);
           }
           const uint64_t bal = __ballot(!settled);
           if (!settled) {
@@ -342,8 +345,8 @@ decode_kernel(DecodeArgs a) {
             ent[1] = wb;
             ent[2] = __float_as_uint(avh[0]);
             ent[3] = __float_as_uint(avh[1]);
-            ent[4] = __float_as_uint(thh[0]);
-            ent[5] = __float_as_uint(thh[1]);
+            ent[4] = __float_as_uint(thr[4 * r + 2 * p]);
+            ent[5] = __float_as_uint(thr[4 * r + 2 * p + 1]);
           }
           total += (uint32_t)__popcll(bal);
         }
@@ -351,9 +354,11 @@ decode_kernel(DecodeArgs a) {
       if (total) flush_list(list, lane, total, qs, pend, posb, flip);
 
       // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
+      if (a.lambda != 1.0f) {
 #pragma unroll
-      for (int q = 0; q < QPL * 4; ++q)
-        if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
+        for (int q = 0; q < QPL * 4; ++q)
+          if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
+      }
       xneg ^= flip;
       if (TRACE) {
 #pragma unroll
