@@ -78,8 +78,9 @@ typedef struct {
  *   out      : receives the handle.
  * The arrays are copied; the column supports M(k) are built here.
  * Errors: NGDBF_EINVAL (bad sizes, indices, empty row or column),
- * NGDBF_EUNSUPPORTED (nnz > 65535 or tables beyond the LDS budget),
- * NGDBF_ENOMEM, NGDBF_EDEVICE.
+ * NGDBF_EUNSUPPORTED (a column degree above 15, an irregular code with more
+ * than 65535 edges), NGDBF_ENOMEM, NGDBF_EDEVICE.  A code whose tables do not
+ * fit the LDS of any launch shape is refused by the decode calls.
  */
 int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr,
                       const int32_t *col_idx, ngdbf_code **out);
@@ -147,6 +148,66 @@ int ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames,
 int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
                       uint64_t seed, uint64_t frame, uint32_t iter,
                       float *out0, float *out1, void *stream);
+
+/*
+ * Launch shape of a code's decode kernel (all shapes give identical results):
+ *   waves_per_frame : wavefronts cooperating on one frame (1, 2, 4, 8, 16);
+ *   quads_per_lane  : bit quads each lane owns (1, 2, 4); a frame holds at most
+ *                     64 * waves_per_frame * quads_per_lane quads (4 bits each);
+ *   frames_per_block: frames per workgroup (1 unless waves_per_frame == 1, then
+ *                     2, 4, 8 or 16).
+ * ngdbf_code_set_shape fixes the shape used by later decodes of this code
+ * (NGDBF_EINVAL if it does not fit the code, NGDBF_EUNSUPPORTED if it was not
+ * built or exceeds the LDS); all-zero arguments restore the default choice.
+ * ngdbf_code_get_shape reports the shape in use (host int32 [3]).
+ * Not thread-safe against concurrent decodes of the same code.
+ */
+int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,
+                         int32_t quads_per_lane, int32_t frames_per_block);
+int ngdbf_code_get_shape(const ngdbf_code *code, int32_t shape[3]);
+
+/*
+ * ngdbf_autotune -- time every built launch shape that fits the code on the
+ * given sample (same arguments as ngdbf_decode; outputs go to scratch the
+ * call allocates and frees) and keep the fastest on the code handle.  The
+ * sample should hold several times the frames the GPU keeps resident (tens of
+ * thousands): on a small sample the shapes that shorten one frame's latency
+ * win, on a large batch those that maximise throughput.
+ *   best : host int32 [3] (may be NULL), receives the chosen shape.
+ *   elapsed_ms : host float (may be NULL), its time on the sample.
+ * Synchronises the stream.  Errors as ngdbf_decode, NGDBF_ENOMEM.
+ */
+int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames,
+                   const float *sigma, float sigma_scalar,
+                   const ngdbf_params *params, uint64_t seed, int32_t best[3],
+                   float *elapsed_ms, void *stream);
+
+/* One independent decode of a batch (fields as the ngdbf_decode arguments). */
+typedef struct {
+    const ngdbf_code *code;
+    const void *y;
+    int64_t n_frames;
+    const float *sigma;
+    float sigma_scalar;
+    ngdbf_params params;
+    uint64_t seed;
+    uint64_t frame_base;
+    uint8_t *out_bits;
+    int32_t *out_iters;
+    uint8_t *out_converged;
+} ngdbf_job;
+
+/*
+ * ngdbf_decode_batch -- decode several jobs (frames of different codes,
+ * parameters and SNRs, Sec. III for each) as one unit of work on `stream`:
+ * the jobs run concurrently on library-owned streams forked from and joined
+ * back to `stream` with events, so the whole batch is one node group when
+ * the caller captures `stream` into a hipGraph.  Every job is validated
+ * before any work is queued.  Results equal those of ngdbf_decode per job.
+ * jobs: host array [n_jobs]; all codes on the current device.
+ * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0), NGDBF_EDEVICE.
+ */
+int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *ngdbf_last_error(void);

@@ -23,7 +23,8 @@ NGDBF_Y_I8 = 1
 
 #: names of the C entry points (include/ngdbf.h)
 ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "ngdbf_decode",
-                 "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_last_error")
+                 "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_code_set_shape",
+                 "ngdbf_code_get_shape", "ngdbf_autotune", "ngdbf_decode_batch", "ngdbf_last_error")
 
 
 class NgdbfError(RuntimeError):
@@ -36,6 +37,14 @@ class ngdbf_params(ctypes.Structure):
     _fields_ = [("w", ctypes.c_float), ("theta", ctypes.c_float), ("lam", ctypes.c_float),
                 ("eta", ctypes.c_float), ("ymax", ctypes.c_float), ("t_max", ctypes.c_int32),
                 ("smooth_window", ctypes.c_int32), ("y_format", ctypes.c_int32)]
+
+
+class ngdbf_job(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n_frames", ctypes.c_int64),
+                ("sigma", ctypes.c_void_p), ("sigma_scalar", ctypes.c_float),
+                ("params", ngdbf_params), ("seed", ctypes.c_uint64),
+                ("frame_base", ctypes.c_uint64), ("out_bits", ctypes.c_void_p),
+                ("out_iters", ctypes.c_void_p), ("out_converged", ctypes.c_void_p)]
 
 
 @dataclasses.dataclass
@@ -76,6 +85,10 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_decode_trace.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64,
                                          U64, P, P, P, P, P]
         L.ngdbf_noise_probe.argtypes = [I32, U32, U32, U64, U64, U32, P, P, P]
+        L.ngdbf_code_set_shape.argtypes = [P, I32, I32, I32]
+        L.ngdbf_code_get_shape.argtypes = [P, P]
+        L.ngdbf_autotune.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, P, P, P]
+        L.ngdbf_decode_batch.argtypes = [ctypes.POINTER(ngdbf_job), I32, P]
         L.ngdbf_last_error.argtypes = []
         L.ngdbf_last_error.restype = ctypes.c_char_p
         for name in ABI_FUNCTIONS:
@@ -155,6 +168,32 @@ def ngdbf_noise_probe(kind: int, start: int, count: int, seed: int, frame: int, 
                                    _addr(out1), _stream(stream)))
 
 
+def ngdbf_code_set_shape(code, waves_per_frame: int, quads_per_lane: int,
+                         frames_per_block: int) -> None:
+    _check(lib().ngdbf_code_set_shape(code, waves_per_frame, quads_per_lane, frames_per_block))
+
+
+def ngdbf_code_get_shape(code):
+    shape = (ctypes.c_int32 * 3)()
+    _check(lib().ngdbf_code_get_shape(code, shape))
+    return tuple(shape)
+
+
+def ngdbf_autotune(code, y, n_frames: int, sigma, sigma_scalar: float, params: ngdbf_params,
+                   seed: int, stream):
+    best = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_float()
+    _check(lib().ngdbf_autotune(code, _addr(y), n_frames, _addr(sigma), sigma_scalar,
+                                ctypes.byref(params), seed, best, ctypes.byref(ms),
+                                _stream(stream)))
+    return tuple(best), ms.value
+
+
+def ngdbf_decode_batch(jobs, stream) -> None:
+    arr = (ngdbf_job * len(jobs))(*jobs)
+    _check(lib().ngdbf_decode_batch(arr, len(jobs), _stream(stream)))
+
+
 def ngdbf_last_error() -> str:
     return lib().ngdbf_last_error().decode()
 
@@ -196,6 +235,44 @@ class Outputs:
     trace: "object" = None  # torch.uint8 [F, T, ceil(n/8)]
 
 
+def _y_format(y) -> int:
+    import torch
+
+    if y.dtype == torch.float32:
+        return NGDBF_Y_F32
+    if y.dtype == torch.int8:
+        return NGDBF_Y_I8
+    raise ValueError("y must be float32 or int8")
+
+
+def alloc_outputs(code: Code, n_frames: int, device) -> Outputs:
+    import torch
+
+    return Outputs(torch.empty((n_frames, code.nbytes_row), dtype=torch.uint8, device=device),
+                   torch.empty(n_frames, dtype=torch.int32, device=device),
+                   torch.empty(n_frames, dtype=torch.uint8, device=device))
+
+
+def job(code: Code, y, sigma, params: Params, seed: int, out: Outputs,
+        frame_base: int = 0) -> ngdbf_job:
+    """One entry of a batch (the tensors must stay alive until it has run)."""
+    import torch
+
+    sig_t, sig_s = (sigma, 0.0) if isinstance(sigma, torch.Tensor) else (None, float(sigma))
+    return ngdbf_job(code.handle.value, _addr(y), y.shape[0], _addr(sig_t), sig_s,
+                     params.c(_y_format(y)), seed, frame_base, _addr(out.bits),
+                     _addr(out.iters), _addr(out.converged))
+
+
+def autotune(code: Code, y, sigma, params: Params, seed: int, stream=None):
+    """Time every launch shape on the sample y and keep the fastest on the code."""
+    import torch
+
+    sig_t, sig_s = (sigma, 0.0) if isinstance(sigma, torch.Tensor) else (None, float(sigma))
+    return ngdbf_autotune(code.handle, y, y.shape[0], sig_t, sig_s, params.c(_y_format(y)), seed,
+                          stream)
+
+
 def decode(code: Code, y, sigma, params: Params, seed: int, frame_base: int = 0,
            trace: bool = False, stream=None, out: Optional[Outputs] = None) -> Outputs:
     """Decode the frames of y (torch [F, n] float32 or int8 on the device).
@@ -208,17 +285,10 @@ def decode(code: Code, y, sigma, params: Params, seed: int, frame_base: int = 0,
         raise ValueError("y must be [frames, n]")
     if not y.is_contiguous():
         raise ValueError("y must be contiguous")
-    if y.dtype == torch.float32:
-        fmt = NGDBF_Y_F32
-    elif y.dtype == torch.int8:
-        fmt = NGDBF_Y_I8
-    else:
-        raise ValueError("y must be float32 or int8")
+    fmt = _y_format(y)
     F = y.shape[0]
     if out is None:
-        out = Outputs(torch.empty((F, code.nbytes_row), dtype=torch.uint8, device=y.device),
-                      torch.empty(F, dtype=torch.int32, device=y.device),
-                      torch.empty(F, dtype=torch.uint8, device=y.device))
+        out = alloc_outputs(code, F, y.device)
         if trace:
             out.trace = torch.empty((F, params.t_max, code.nbytes_row), dtype=torch.uint8,
                                     device=y.device)

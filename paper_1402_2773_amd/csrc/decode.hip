@@ -42,6 +42,8 @@ constexpr int kWave = 64;
 constexpr int kListCap = 256;
 // a list entry: the pair's two Philox words, a_k and theta_k of both bits
 constexpr int kEntryWords = 6;
+// check-toggle events per frame and round held for the parallel u update
+constexpr int kEventCap = 256;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 
@@ -67,6 +69,7 @@ struct DecodeArgs {
   uint8_t *trace;
   int32_t frames_per_block;               // frame slots per workgroup
   int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
+  uint32_t dc_recip;                      // ceil(2^20 / d_c) for regular codes
   int32_t slot_words;                     // LDS words per frame slot
 };
 
@@ -175,7 +178,7 @@ struct Tables {
 // no transform.  The test runs on squares with a 4e-5 relative slack that
 // covers all rounding.  Every other pair goes through the transform.
 template <int WPF, int QPL, int YFMT, bool TRACE, bool REG>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 decode_kernel(DecodeArgs a) {
   extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
@@ -205,6 +208,8 @@ decode_kernel(DecodeArgs a) {
   uint32_t *xw = uw + a.uw_words;          // [xw_words] x / output bits
   uint32_t *fw = xw + a.xw_words;          // [xw_words] flip bits (trace)
   uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
+  uint32_t *evn = cnt + 1;                 // events listed this round
+  uint32_t *evl = evn + 1;                 // [kEventCap] toggle events
   uint32_t *list = lds + a.table_words + a.frames_per_block * a.slot_words + wave * (kEntryWords * kListCap);
   __syncthreads();
 
@@ -323,11 +328,12 @@ decode_kernel(DecodeArgs a) {
           for (int h = 0; h < 2; ++h) {
             const int b = 2 * p + h;
             const int q = 4 * r + b;
-            const int deg = REG ? a.dv : (int)((deg4[r] >> (4 * b)) & 15u);
-            const int S = deg - 2 * (int)((u4 >> (8 * b)) & 255u);
+            // S_k = deg_k - 2 u_k, formed exactly in binary32
+            const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
+            const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
             // x_k y_k: flip the sign bit of y_k when x_k = -1 (exact)
             const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
-            const float av = __builtin_fmaf(a.w, (float)S, xy);
+            const float av = __builtin_fmaf(a.w, Sf, xy);
             const float mg = av - thr[q];
             avh[h] = av;
             // settled without a draw: a_k - theta_k >= qs * bound (no flip);
@@ -369,6 +375,8 @@ decode_kernel(DecodeArgs a) {
         }
       }
       frame_sync<WPF>();  // every wave has read u before any toggle lands
+      // each flip toggles s_i of its checks; each toggle is an event (i, +-1)
+      // for the u of the check's bits, applied below by all lanes at once
       uint32_t fl = flip;
       int32_t dcnt = 0;
       while (fl) {
@@ -381,17 +389,39 @@ decode_kernel(DecodeArgs a) {
           const int i = tab.row_idx[e];
           const uint32_t old = atomicXor(&sw[i >> 5], 1u << (i & 31));
           const bool became_unsat = ((old >> (i & 31)) & 1u) == 0u;
-          const uint32_t d = became_unsat ? 1u : 0xFFFFFFFFu;  // +1 / -1
           dcnt += became_unsat ? 1 : -1;
-          const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
-#pragma unroll 4
-          for (int e2 = r0; e2 < r1; ++e2) {
-            const int k2 = tab.col_idx[e2];
-            atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
+          const uint32_t ev = ((uint32_t)i << 1) | (became_unsat ? 0u : 1u);
+          const uint32_t slotn = REG ? atomicAdd(evn, 1u) : (uint32_t)kEventCap;
+          if (slotn < (uint32_t)kEventCap) {
+            evl[slotn] = ev;
+          } else {
+            // list full (or an irregular code): apply the event here
+            const uint32_t d = became_unsat ? 1u : 0xFFFFFFFFu;
+            const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
+            for (int e2 = r0; e2 < r1; ++e2) {
+              const int k2 = tab.col_idx[e2];
+              atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
+            }
           }
         }
       }
       if (dcnt) atomicAdd(cnt, (uint32_t)dcnt);
+      if (REG) {
+        frame_sync<WPF>();
+        const uint32_t nev = *(volatile uint32_t *)evn;
+        const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
+        const uint32_t nup = listed * (uint32_t)a.dc;  // one u update per lane
+        for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {
+          const uint32_t e = (x * a.dc_recip) >> 20;    // x / d_c, exact here
+          const uint32_t ev = evl[e];
+          const int i = (int)(ev >> 1);
+          const uint32_t d = (ev & 1u) ? 0xFFFFFFFFu : 1u;
+          const int k2 = tab.col_idx[i * a.dc + (int)(x - e * a.dc)];
+          atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
+        }
+        frame_sync<WPF>();
+        if (ft == 0) *evn = 0u;
+      }
       frame_sync<WPF>();
       if (TRACE) {
         uint8_t *row = a.trace + ((size_t)f * (size_t)T + (size_t)t) * (size_t)nbytes;
@@ -470,6 +500,7 @@ struct ngdbf_code {
   int32_t off_row, off_rowptr, off_colptr;
   int32_t dv, dc;      // uniform degrees (0 if irregular)
   int32_t max_col_deg, max_row_deg;
+  int32_t shape[3];    // fixed launch shape (waves/frame, quads/lane, frames/block), 0 = default
 };
 
 namespace {
@@ -490,44 +521,96 @@ int ok() {
   return NGDBF_OK;
 }
 
-struct DeviceInfo {
+// ---------------------------------------------------------------- devices
+
+struct DeviceState {
   int cus = 0;
+  std::mutex mu;                      // guards the fork/join pool below
+  std::vector<hipStream_t> streams;   // library streams for batched jobs
+  std::vector<hipEvent_t> events;     // one per stream, plus the fork event
+  hipEvent_t fork = nullptr;
 };
 
-DeviceInfo device_info(int dev) {
+DeviceState &device_state(int dev) {
   static std::mutex mu;
-  static std::vector<DeviceInfo> cache;
+  static std::vector<DeviceState *> all;
   std::lock_guard<std::mutex> g(mu);
-  if ((int)cache.size() <= dev) cache.resize(dev + 1);
-  if (cache[dev].cus == 0) {
+  if ((int)all.size() <= dev) all.resize(dev + 1, nullptr);
+  if (!all[dev]) {
+    all[dev] = new DeviceState();  // lives until the process ends
     hipDeviceProp_t p;
-    if (hipGetDeviceProperties(&p, dev) == hipSuccess) cache[dev].cus = p.multiProcessorCount;
+    if (hipGetDeviceProperties(&p, dev) == hipSuccess) all[dev]->cus = p.multiProcessorCount;
   }
-  return cache[dev];
+  return *all[dev];
 }
 
-// Launch shape for a code: WPF waves per frame, QPL quads per lane.
+// ---------------------------------------------------------------- shapes
+
 struct Shape {
-  int wpf, qpl, block, fpb;
+  int wpf, qpl, fpb;
+  int block() const { return 64 * wpf * fpb; }
 };
 
-int choose_shape(int n, Shape *s) {
-  const int nq = (n + 3) / 4;
-  for (int wpf : {1, 2, 4}) {
-    for (int qpl : {1, 2, 4}) {
-      if (nq <= wpf * 64 * qpl) {
-        // one frame per wave, four per workgroup; a frame spanning several
-        // waves is a workgroup of its own (its barriers are per frame)
-        s->wpf = wpf;
-        s->qpl = qpl;
-        s->fpb = wpf == 1 ? 8 : 1;
-        s->block = wpf == 1 ? 512 : 64 * wpf;
-        return NGDBF_OK;
+// (waves per frame, quads per lane) pairs with built kernels
+constexpr int kShapes[][2] = {{1, 1}, {1, 2}, {1, 4}, {2, 2}, {2, 4}, {4, 1},
+                              {4, 2}, {4, 4}, {8, 1}, {8, 2}, {16, 1}};
+
+bool shape_built(int wpf, int qpl) {
+  for (const auto &sh : kShapes)
+    if (sh[0] == wpf && sh[1] == qpl) return true;
+  return false;
+}
+
+size_t slot_words(const ngdbf_code *c, bool trace) {
+  return (size_t)((c->m + 31) / 32) + (size_t)((c->n + 3) / 4) +
+         (size_t)((c->n + 31) / 32) * (trace ? 2 : 1) + 2 + ngdbf::kEventCap;
+}
+
+size_t lds_bytes(const ngdbf_code *c, const Shape &sh, bool trace) {
+  return ((size_t)c->table_words + (size_t)sh.fpb * slot_words(c, trace) +
+          (size_t)(sh.block() / 64) * ngdbf::kEntryWords * ngdbf::kListCap) * 4;
+}
+
+// NGDBF_OK if the shape can decode the code, else an error with a message
+int check_shape(const ngdbf_code *c, const Shape &sh, bool trace) {
+  const int nq = (c->n + 3) / 4;
+  if (!shape_built(sh.wpf, sh.qpl))
+    return fail(NGDBF_EUNSUPPORTED, "no kernel for %d waves x %d quads", sh.wpf, sh.qpl);
+  if (nq > 64 * sh.wpf * sh.qpl)
+    return fail(NGDBF_EINVAL, "%d waves x %d quads hold %d quads, the code has %d", sh.wpf,
+                sh.qpl, 64 * sh.wpf * sh.qpl, nq);
+  if (sh.wpf > 1 && sh.fpb != 1)
+    return fail(NGDBF_EINVAL, "a frame of several waves is a workgroup of its own");
+  if (sh.fpb < 1 || sh.block() > 1024)
+    return fail(NGDBF_EINVAL, "workgroup of %d threads", sh.block());
+  if (lds_bytes(c, sh, trace) > 160 * 1024)
+    return fail(NGDBF_EUNSUPPORTED, "shape needs %zu B of LDS", lds_bytes(c, sh, trace));
+  return NGDBF_OK;
+}
+
+// The code's fixed shape, or the default: the fewest waves per frame, then
+// the fewest quads per lane that hold the code; eight single-wave frames per
+// workgroup, which then share one copy of the code tables.
+int pick_shape(const ngdbf_code *c, bool trace, Shape *out) {
+  if (c->shape[0]) {
+    *out = Shape{c->shape[0], c->shape[1], c->shape[2]};
+    return check_shape(c, *out, trace);
+  }
+  const int nq = (c->n + 3) / 4;
+  for (const auto &sh : kShapes) {
+    if (nq <= 64 * sh[0] * sh[1]) {
+      Shape cand{sh[0], sh[1], sh[0] == 1 ? 8 : 1};
+      while (check_shape(c, cand, trace) != NGDBF_OK && cand.fpb > 1) cand.fpb /= 2;
+      if (check_shape(c, cand, trace) == NGDBF_OK) {
+        *out = cand;
+        return ok();
       }
     }
   }
-  return fail(NGDBF_EUNSUPPORTED, "n = %d exceeds the 4096 bits one workgroup decodes", n);
+  return fail(NGDBF_EUNSUPPORTED, "no launch shape fits n = %d", c->n);
 }
+
+// ---------------------------------------------------------------- launch
 
 template <int WPF, int QPL, int YFMT, bool TRACE, bool REG>
 int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int dev, hipStream_t s) {
@@ -537,15 +620,16 @@ int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int de
                           (int)lds_bytes) != hipSuccess)
     return fail(NGDBF_EUNSUPPORTED, "cannot raise the LDS limit to %zu bytes", lds_bytes);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, sh.block, lds_bytes) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, sh.block(), lds_bytes) !=
+          hipSuccess ||
       per_cu <= 0)
     return fail(NGDBF_EUNSUPPORTED, "kernel does not fit a compute unit (block %d, LDS %zu B)",
-                sh.block, lds_bytes);
-  const DeviceInfo di = device_info(dev);
+                sh.block(), lds_bytes);
+  const int cus = std::max(device_state(dev).cus, 1);
   const int64_t blocks_needed = (a.n_frames + sh.fpb - 1) / sh.fpb;
-  int64_t grid = (int64_t)per_cu * std::max(di.cus, 1);
-  grid = std::min<int64_t>(grid, blocks_needed);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.block), lds_bytes, s, a);
+  // persistent grid: the resident capacity, or fewer blocks for small batches
+  const int64_t grid = std::min<int64_t>((int64_t)per_cu * cus, blocks_needed);
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.block()), lds_bytes, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   return ok();
@@ -560,8 +644,14 @@ int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, h
   NGDBF_CASE(1, 1)
   NGDBF_CASE(1, 2)
   NGDBF_CASE(1, 4)
+  NGDBF_CASE(2, 2)
   NGDBF_CASE(2, 4)
+  NGDBF_CASE(4, 1)
+  NGDBF_CASE(4, 2)
   NGDBF_CASE(4, 4)
+  NGDBF_CASE(8, 1)
+  NGDBF_CASE(8, 2)
+  NGDBF_CASE(16, 1)
 #undef NGDBF_CASE
   return fail(NGDBF_EUNSUPPORTED, "no kernel for %d waves x %d quads", sh.wpf, sh.qpl);
 }
@@ -576,15 +666,26 @@ int check_params(const ngdbf_params *p) {
   if (std::isnan(p->ymax)) return fail(NGDBF_EINVAL, "ymax is NaN");
   if (p->t_max < 0 || p->t_max > 65535) return fail(NGDBF_EINVAL, "t_max must be in [0, 65535]");
   if (p->smooth_window < 0) return fail(NGDBF_EINVAL, "smooth_window must be >= 0");
+  if (p->smooth_window > 0 && std::min(p->smooth_window, p->t_max) >= 32767)
+    return fail(NGDBF_EUNSUPPORTED, "smoothing over more than 32767 rounds");
   if (p->y_format != NGDBF_Y_F32 && p->y_format != NGDBF_Y_I8)
     return fail(NGDBF_EINVAL, "unknown y_format %d", p->y_format);
   return NGDBF_OK;
 }
 
-int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
-                  float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
-                  uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
-                  void *stream) {
+// Everything a launch needs, validated on the host before any device work.
+struct Prepared {
+  ngdbf::DecodeArgs a;
+  Shape sh;
+  size_t lds;
+  int dev;
+  int y_format;
+};
+
+int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+            float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
+            uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
+            const Shape *force, Prepared *out) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   int rc = check_params(p);
   if (rc) return rc;
@@ -597,26 +698,16 @@ int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const
   if (hipGetDevice(&dev) != hipSuccess) return fail(NGDBF_EDEVICE, "no HIP device");
   if (dev != code->device)
     return fail(NGDBF_EINVAL, "code lives on device %d, current device is %d", code->device, dev);
-  // report an earlier asynchronous fault before queueing more work
-  const hipError_t pending = hipGetLastError();
-  if (pending != hipSuccess)
-    return fail(NGDBF_EDEVICE, "earlier HIP error: %s", hipGetErrorString(pending));
-  hipStream_t s = (hipStream_t)stream;
-  const int n = code->n, m = code->m;
-  const int nbytes = (n + 7) / 8;
-  if (trace && n_frames > 0 && p->t_max > 0) {
-    const size_t tb = (size_t)n_frames * (size_t)p->t_max * (size_t)nbytes;
-    if (hipMemsetAsync(trace, 0, tb, s) != hipSuccess)
-      return fail(NGDBF_EDEVICE, "trace clear failed");
-  }
-  if (n_frames == 0) return ok();
-
   Shape sh;
-  rc = choose_shape(n, &sh);
+  if (force) {
+    sh = *force;
+    rc = check_shape(code, sh, trace != nullptr);
+  } else {
+    rc = pick_shape(code, trace != nullptr, &sh);
+  }
   if (rc) return rc;
-  if (p->smooth_window > 0 && std::min(p->smooth_window, p->t_max) >= 32767)
-    return fail(NGDBF_EUNSUPPORTED, "smoothing over more than 32767 rounds");
-  ngdbf::DecodeArgs a;
+  const int n = code->n, m = code->m;
+  ngdbf::DecodeArgs &a = out->a;
   a.tables = code->d_tables;
   a.table_words = code->table_words;
   a.off_row = code->off_row;
@@ -648,16 +739,50 @@ int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const
   a.sw_words = (m + 31) / 32;
   a.uw_words = (n + 3) / 4;
   a.xw_words = (n + 31) / 32;
-  a.slot_words = a.sw_words + a.uw_words + a.xw_words * (trace ? 2 : 1) + 1;
-  const size_t lds = ((size_t)a.table_words + (size_t)sh.fpb * a.slot_words +
-                      (size_t)(sh.block / 64) * ngdbf::kEntryWords * ngdbf::kListCap) * 4;
-  if (lds > 160 * 1024) return fail(NGDBF_EUNSUPPORTED, "code needs %zu B of LDS", lds);
-  if (p->y_format == NGDBF_Y_I8) {
-    return trace ? dispatch<NGDBF_Y_I8, true>(sh, a, lds, dev, s)
-                 : dispatch<NGDBF_Y_I8, false>(sh, a, lds, dev, s);
+  a.slot_words = (int32_t)slot_words(code, trace != nullptr);
+  a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
+  out->sh = sh;
+  out->lds = lds_bytes(code, sh, trace != nullptr);
+  out->dev = dev;
+  out->y_format = p->y_format;
+  return ok();
+}
+
+int enqueue(const Prepared &pr, hipStream_t s) {
+  if (pr.a.n_frames == 0) return ok();
+  const bool trace = pr.a.trace != nullptr;
+  if (pr.y_format == NGDBF_Y_I8) {
+    return trace ? dispatch<NGDBF_Y_I8, true>(pr.sh, pr.a, pr.lds, pr.dev, s)
+                 : dispatch<NGDBF_Y_I8, false>(pr.sh, pr.a, pr.lds, pr.dev, s);
   }
-  return trace ? dispatch<NGDBF_Y_F32, true>(sh, a, lds, dev, s)
-               : dispatch<NGDBF_Y_F32, false>(sh, a, lds, dev, s);
+  return trace ? dispatch<NGDBF_Y_F32, true>(pr.sh, pr.a, pr.lds, pr.dev, s)
+               : dispatch<NGDBF_Y_F32, false>(pr.sh, pr.a, pr.lds, pr.dev, s);
+}
+
+int pending_error() {
+  // report an earlier asynchronous fault before queueing more work
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(NGDBF_EDEVICE, "earlier HIP error: %s", hipGetErrorString(e));
+  return NGDBF_OK;
+}
+
+int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+                  float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
+                  uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
+                  void *stream) {
+  Prepared pr;
+  int rc = prepare(code, y, n_frames, sigma, sigma_scalar, p, seed, frame_base, out_bits,
+                   out_iters, out_conv, trace, nullptr, &pr);
+  if (rc) return rc;
+  rc = pending_error();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (trace && n_frames > 0 && p->t_max > 0) {
+    const size_t tb = (size_t)n_frames * (size_t)p->t_max * (size_t)((code->n + 7) / 8);
+    if (hipMemsetAsync(trace, 0, tb, s) != hipSuccess)
+      return fail(NGDBF_EDEVICE, "trace clear failed");
+  }
+  return enqueue(pr, s);
 }
 
 }  // namespace
@@ -741,6 +866,7 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   c->dc = regular ? maxr : 0;
   c->max_row_deg = maxr;
   c->max_col_deg = maxc;
+  c->shape[0] = c->shape[1] = c->shape[2] = 0;
   const size_t bytes = (size_t)words * 4;
   if (hipMalloc((void **)&c->d_tables, bytes) != hipSuccess) {
     free(c);
@@ -814,6 +940,163 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t see
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "probe launch failed: %s", hipGetErrorString(e));
   return ok();
+}
+
+int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quads_per_lane,
+                         int32_t frames_per_block) {
+  if (!code) return fail(NGDBF_EINVAL, "code is NULL");
+  if (!waves_per_frame && !quads_per_lane && !frames_per_block) {
+    code->shape[0] = code->shape[1] = code->shape[2] = 0;
+    return ok();
+  }
+  const Shape sh{waves_per_frame, quads_per_lane, frames_per_block};
+  int rc = check_shape(code, sh, false);
+  if (rc) return rc;
+  code->shape[0] = sh.wpf;
+  code->shape[1] = sh.qpl;
+  code->shape[2] = sh.fpb;
+  return ok();
+}
+
+int ngdbf_code_get_shape(const ngdbf_code *code, int32_t shape[3]) {
+  if (!code || !shape) return fail(NGDBF_EINVAL, "code and shape are required");
+  Shape sh;
+  int rc = pick_shape(code, false, &sh);
+  if (rc) return rc;
+  shape[0] = sh.wpf;
+  shape[1] = sh.qpl;
+  shape[2] = sh.fpb;
+  return ok();
+}
+
+int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+                   float sigma_scalar, const ngdbf_params *params, uint64_t seed, int32_t best[3],
+                   float *elapsed_ms, void *stream) {
+  if (!code) return fail(NGDBF_EINVAL, "code is NULL");
+  if (n_frames <= 0) return fail(NGDBF_EINVAL, "autotuning needs a sample of frames");
+  int rc = pending_error();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nb = (size_t)(code->n + 7) / 8;
+  uint8_t *bits = nullptr;
+  int32_t *iters = nullptr;
+  if (hipMalloc((void **)&bits, (size_t)n_frames * nb) != hipSuccess ||
+      hipMalloc((void **)&iters, (size_t)n_frames * 4) != hipSuccess) {
+    (void)hipFree(bits);
+    return fail(NGDBF_ENOMEM, "autotune scratch of %lld frames", (long long)n_frames);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  Shape best_sh{0, 0, 0};
+  float best_ms = 0.0f;
+  const int nq = (code->n + 3) / 4;
+  for (const auto &ks : kShapes) {
+    if (nq > 64 * ks[0] * ks[1]) continue;
+    // more quads per lane or waves per frame than the code needs only idle lanes
+    if (ks[1] > 1 && nq <= 64 * ks[0] * (ks[1] / 2)) continue;
+    if (ks[0] > 1 && nq <= 64 * (ks[0] / 2) * ks[1]) continue;
+    for (int fpb : {1, 2, 4, 8, 16}) {
+      const Shape cand{ks[0], ks[1], fpb};
+      if (check_shape(code, cand, false) != NGDBF_OK) continue;
+      Prepared pr;
+      rc = prepare(code, y, n_frames, sigma, sigma_scalar, params, seed, 0, bits, iters, nullptr,
+                   nullptr, &cand, &pr);
+      if (rc) break;
+      rc = enqueue(pr, s);  // warm-up
+      if (rc == NGDBF_EUNSUPPORTED) {  // rejected before launch (occupancy, LDS)
+        rc = NGDBF_OK;
+        continue;
+      }
+      if (rc) break;
+      (void)hipEventRecord(e0, s);
+      for (int rep = 0; rep < 2 && !rc; ++rep) rc = enqueue(pr, s);
+      (void)hipEventRecord(e1, s);
+      if (rc) break;
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(NGDBF_EDEVICE, "autotune run failed");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms *= 0.5f;
+      if (!best_sh.wpf || ms < best_ms) {
+        best_sh = cand;
+        best_ms = ms;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(bits);
+  (void)hipFree(iters);
+  if (rc) return rc;
+  if (!best_sh.wpf) return fail(NGDBF_EUNSUPPORTED, "no launch shape fits this code");
+  code->shape[0] = best_sh.wpf;
+  code->shape[1] = best_sh.qpl;
+  code->shape[2] = best_sh.fpb;
+  if (best) {
+    best[0] = best_sh.wpf;
+    best[1] = best_sh.qpl;
+    best[2] = best_sh.fpb;
+  }
+  if (elapsed_ms) *elapsed_ms = best_ms;
+  return ok();
+}
+
+int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(NGDBF_EINVAL, "bad job array");
+  std::vector<Prepared> prs((size_t)n_jobs);
+  for (int i = 0; i < n_jobs; ++i) {
+    const ngdbf_job &j = jobs[i];
+    const int rc = prepare(j.code, j.y, j.n_frames, j.sigma, j.sigma_scalar, &j.params, j.seed,
+                           j.frame_base, j.out_bits, j.out_iters, j.out_converged, nullptr,
+                           nullptr, &prs[i]);
+    if (rc) {
+      char msg[512];
+      snprintf(msg, sizeof msg, "%s", g_err);
+      return fail(rc, "job %d: %s", i, msg);
+    }
+    if (i && prs[i].dev != prs[0].dev) return fail(NGDBF_EINVAL, "jobs span several devices");
+  }
+  int rc = pending_error();
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (n_jobs == 0) return ok();
+  if (n_jobs == 1) return enqueue(prs[0], s);
+  DeviceState &ds = device_state(prs[0].dev);
+  std::lock_guard<std::mutex> g(ds.mu);
+  const size_t lanes = (size_t)std::min(n_jobs, 8);
+  while (ds.streams.size() < lanes) {
+    hipStream_t ns = nullptr;
+    hipEvent_t ne = nullptr;
+    // default priority: library streams never outrank the caller's work
+    if (hipStreamCreateWithFlags(&ns, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ne, hipEventDisableTiming) != hipSuccess)
+      return fail(NGDBF_EDEVICE, "cannot create the batch streams");
+    ds.streams.push_back(ns);
+    ds.events.push_back(ne);
+  }
+  if (!ds.fork && hipEventCreateWithFlags(&ds.fork, hipEventDisableTiming) != hipSuccess)
+    return fail(NGDBF_EDEVICE, "cannot create the fork event");
+  // fork: every library stream waits for the work already queued on `stream`
+  if (hipEventRecord(ds.fork, s) != hipSuccess) return fail(NGDBF_EDEVICE, "fork record failed");
+  for (size_t l = 0; l < lanes; ++l)
+    if (hipStreamWaitEvent(ds.streams[l], ds.fork, 0) != hipSuccess)
+      return fail(NGDBF_EDEVICE, "fork wait failed");
+  for (int i = 0; i < n_jobs; ++i) {
+    rc = enqueue(prs[i], ds.streams[(size_t)i % lanes]);
+    if (rc) break;
+  }
+  // join: `stream` waits for every library stream (also after a failure, so
+  // that the fork/join structure stays balanced under graph capture)
+  for (size_t l = 0; l < lanes; ++l) {
+    if (hipEventRecord(ds.events[l], ds.streams[l]) != hipSuccess ||
+        hipStreamWaitEvent(s, ds.events[l], 0) != hipSuccess)
+      return fail(NGDBF_EDEVICE, "join failed");
+  }
+  return rc;
 }
 
 }  // extern "C"

@@ -72,3 +72,15 @@ def test_params_struct_layout_matches_header():
     assert ctypes.sizeof(ng.ngdbf_params) == 32
     names = [f[0] for f in ng.ngdbf_params._fields_]
     assert names == ["w", "theta", "lam", "eta", "ymax", "t_max", "smooth_window", "y_format"]
+
+
+def test_batch_and_shape_reject_bad_arguments(L):
+    with pytest.raises(ng.NgdbfError, match="bad job array"):
+        L_status = ng.lib().ngdbf_decode_batch(None, -1, None)
+        ng._check(L_status)
+    with pytest.raises(ng.NgdbfError, match="code is NULL"):
+        ng.ngdbf_code_set_shape(None, 1, 4, 8)
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    bad = ng.ngdbf_job(None, None, 0, None, 0.5, p, 1, 0, None, None, None)
+    with pytest.raises(ng.NgdbfError, match="job 0: code is NULL"):
+        ng.ngdbf_decode_batch([bad], 0)
