@@ -218,15 +218,148 @@ def run_mix4(args) -> int:
     return 0
 
 
+def run_serve(args) -> int:
+    """Open-loop serving: Poisson request arrivals at --serve-rate req/s for
+    --serve-seconds, frames per request log-uniform in [1, 4096], code uniform
+    over the four codes, per-request Eb/N0 ~ U[2, 5] dB, decoder seed = request
+    id.  The same arrival sequence is served twice by the native runtime:
+    continuously batched (every committed request of a code joins one launch)
+    and with one launch per request.  Latency runs from a request's scheduled
+    arrival to the host seeing it finished; requests still queued when the
+    arrival window closes are reported as unserved."""
+    import numpy as np
+    import torch
+
+    import paper_1402_2773_amd as ng
+    from synth import channel, codes
+
+    names = [name for name, _, _ in MIX4]
+    params = [ng.Params(**pr) for _, _, pr in MIX4]
+    cl = [codes.named_code(nm) for nm in names]
+    dcs = [ng.Code.from_ldpc(c) for c in cl]
+    pool = [1 << 18, 1 << 18, 1 << 17, 1 << 16]  # resident slots per code (1 GiB of y at most)
+    rng = np.random.default_rng(int(args.serve_rate) + 17)
+    n_req = int(rng.poisson(args.serve_rate * args.serve_seconds))
+    t_arr = np.sort(rng.uniform(0.0, args.serve_seconds, n_req))  # Poisson process
+    n_fr = np.minimum(np.exp(rng.uniform(0.0, math.log(4097.0), n_req)).astype(np.int64), 4096)
+    n_fr = np.maximum(n_fr, 1)
+    code_of = rng.integers(0, len(names), n_req).astype(np.int32)
+    ebn0 = rng.uniform(2.0, 5.0, n_req)
+    rates = np.array([c.rate for c in cl])
+    sig_req = (1.0 / np.sqrt(2.0 * rates[code_of] * 10.0 ** (ebn0 / 10.0))).astype(np.float32)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4242)
+
+    def serve(max_per_launch: int, window: float):
+        srv = ng.Server(dcs, params, pool, n_streams=4, max_requests_per_launch=max_per_launch)
+        queues = [np.nonzero(code_of == c)[0] for c in range(len(names))]
+        q_t = [t_arr[q] for q in queues]
+        qpos = [0] * len(names)
+        live = {}
+        t_done = np.full(n_req, np.nan)
+        launches = 0
+        stream = torch.cuda.current_stream()
+
+        def fill(c, idx, first):
+            frames = n_fr[idx]
+            tot = int(frames.sum())
+            starts = np.repeat(first - np.concatenate(([0], np.cumsum(frames)[:-1])), frames)
+            slots = torch.from_numpy(starts + np.arange(tot)).cuda(non_blocking=True)
+            sig = torch.from_numpy(np.repeat(sig_req[idx], frames)).cuda(non_blocking=True)
+            y = torch.randn((tot, cl[c].n), generator=gen, device="cuda").mul_(sig[:, None]).add_(1.0)
+            srv.pools[c].y.index_copy_(0, slots, y)
+            srv.pools[c].sigma.index_copy_(0, slots, sig)
+
+        # warm-up: one request per code, outside the window
+        for c in range(len(names)):
+            t, first = srv.admit([c], [64], [1 << 40], [0])
+            srv.pools[c].y[first[0]:first[0] + 64].fill_(1.0)
+            srv.pools[c].sigma[first[0]:first[0] + 64].fill_(0.5)
+            srv.commit(t, stream)
+        got = 0
+        while got < len(names):
+            srv.pump()
+            d = srv.poll()
+            got += len(d)
+            srv.release(d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            now = time.perf_counter() - t0
+            open_ = now < window
+            if open_:
+                for c in range(len(names)):
+                    q = queues[c]
+                    lo = qpos[c]
+                    hi = int(np.searchsorted(q_t[c], now, side="right"))
+                    if hi <= lo:
+                        continue
+                    idx = q[lo:min(hi, lo + 1024)]
+                    tickets, first = srv.admit(np.full(len(idx), c, np.int32), n_fr[idx], idx.astype(np.uint64),
+                                               np.zeros(len(idx), np.uint64))
+                    k = len(tickets)
+                    if k:
+                        fill(c, idx[:k], first)
+                        srv.commit(tickets, stream)
+                        for tk, r in zip(tickets.tolist(), idx[:k].tolist()):
+                            live[tk] = r
+                        qpos[c] += k
+            launches += srv.pump()
+            done = srv.poll()
+            if len(done):
+                tnow = time.perf_counter() - t0
+                for tk in done.tolist():
+                    t_done[live.pop(tk)] = tnow
+                srv.release(done)
+            if not open_ and not live:
+                break
+        srv.close()
+        ok = ~np.isnan(t_done)
+        lat = (t_done[ok] - t_arr[ok]) * 1e3
+        span = float(np.nanmax(t_done)) if ok.any() else window
+        frames_done = int(n_fr[ok].sum())
+        info = float(sum(int(n_fr[ok & (code_of == c)].sum()) * cl[c].k_info for c in range(len(names))))
+        return {"served_requests": int(ok.sum()), "unserved_requests": int((~ok).sum()),
+                "frames": frames_done, "launches": launches,
+                "info_gbps": info / span / 1e9, "frames_per_s": frames_done / span,
+                "span_s": span,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)) if len(lat) else None,
+                               "p99": float(np.percentile(lat, 99)) if len(lat) else None,
+                               "p99.9": float(np.percentile(lat, 99.9)) if len(lat) else None}}
+
+    batched = serve(4096, args.serve_seconds)
+    print(f"# batched: {batched}", file=sys.stderr, flush=True)
+    single = serve(1, args.serve_seconds) if not args.serve_batched_only else None
+    result = {
+        "metric": METRIC, "value": batched["info_gbps"], "unit": "Gbit/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": batched["span_s"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN, Poisson arrivals",
+        "config": {"workload": "serve", "rate_req_per_s": args.serve_rate,
+                   "window_s": args.serve_seconds, "requests": n_req,
+                   "offered_frames": int(n_fr.sum()), "codes": names, "pool_slots": pool,
+                   "description": "continuous batching over resident slot pools, 4 codes, "
+                                  "frames/request log-uniform [1,4096], Eb/N0 ~ U[2,5] dB"},
+        "latency_ms": batched["latency_ms"], "batched": batched, "per_request_launch": single,
+    }
+    print(json.dumps(result), flush=True)
+    for d in dcs:
+        d.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["mix4"])
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["mix4", "serve"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: arrival window")
+    ap.add_argument("--serve-batched-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -255,6 +388,8 @@ def main() -> int:
         del src_t, dst_t
     if args.workload == "mix4":
         return run_mix4(args)
+    if args.workload == "serve":
+        return run_serve(args)
     code_name, ebn0, params, frames, yfmt, desc = WORKLOADS[args.workload]
     if args.frames:
         frames = args.frames

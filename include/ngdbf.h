@@ -209,6 +209,117 @@ typedef struct {
  */
 int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
 
+/*
+ * Segmented decoding: frames scattered over slot ranges of resident pools.
+ * Segment s covers launch frames [frame_offset_s, frame_offset_{s+1}) (the last
+ * one up to n_frames); its frames live at pool slots first_slot_s, ... and are
+ * keyed for the noise as (seed_s, frame_base_s + i).  A frame therefore
+ * decodes exactly as ngdbf_decode would decode it with that seed and frame
+ * index, whatever else shares the launch.
+ */
+typedef struct {
+    int64_t first_slot;    /* pool slot of the segment's first frame              */
+    int64_t frame_offset;  /* launch index of that frame; 0 for the first segment,
+                              strictly increasing                                  */
+    uint64_t seed;         /* Philox key of the segment                            */
+    uint64_t frame_base;   /* noise frame index of the segment's first frame       */
+} ngdbf_segment;
+
+/*
+ * ngdbf_decode_segments -- decode n_frames frames given as segments.
+ *   y_pool, sigma_pool : dev [pool_frames][n] float32 / int8 and [pool_frames]
+ *                        (sigma_pool may be NULL: sigma_scalar for all).
+ *   segments           : dev ngdbf_segment [n_segments], n_segments >= 1.
+ *   bits_pool, iters_pool, conv_pool : dev pools indexed by slot like y_pool
+ *                        (conv_pool may be NULL).
+ * The caller guarantees that every segment's slots lie in [0, pool_frames);
+ * a frame whose slot falls outside is skipped (nothing is read or written).
+ * Errors as ngdbf_decode.
+ */
+int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool,
+                          const float *sigma_pool, float sigma_scalar,
+                          int64_t pool_frames, const ngdbf_params *params,
+                          const ngdbf_segment *segments, int32_t n_segments,
+                          int64_t n_frames, uint8_t *bits_pool,
+                          int32_t *iters_pool, uint8_t *conv_pool, void *stream);
+
+/*
+ * Serving runtime: continuous batching of decode requests (Sec. III per
+ * frame) over pools of frame slots kept resident in HBM.  A request is a run
+ * of frames of one code with its own noise key (seed, frame_base); its results
+ * equal those of a standalone ngdbf_decode of its frames with that key,
+ * whatever it shares a launch with.  All calls on one server are serialised
+ * internally; the server, its pools and streams belong to the device current
+ * at creation.  Errors: NGDBF_EINVAL (bad argument, unknown or wrong-state
+ * ticket), NGDBF_ENOMEM (pools do not fit), NGDBF_EDEVICE (HIP failure, or a
+ * launch that failed on the device, reported by poll).
+ */
+typedef struct ngdbf_server ngdbf_server;
+
+/*
+ * ngdbf_server_create -- one slot pool per code: y float32 [pool_frames_i][n_i],
+ * sigma float32 [pool_frames_i], bits [pool_frames_i][ceil(n_i/8)], iterations
+ * int32 and converged uint8 [pool_frames_i], all owned by the server.
+ *   codes, params, pool_frames : host arrays [n_codes]; params[i].y_format must
+ *                                be NGDBF_Y_F32; the codes must outlive the server.
+ *   n_streams                  : library streams the launches rotate over, [1, 16].
+ *   max_requests_per_launch    : [1, 4096]; 1 gives one launch per request (the
+ *                                unbatched baseline), larger values batch.
+ *   out                        : receives the handle (NULL on failure).
+ */
+int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes,
+                        const ngdbf_params *params, const int64_t *pool_frames,
+                        int32_t n_streams, int32_t max_requests_per_launch,
+                        ngdbf_server **out);
+/* Waits for launches in flight, then frees everything the server owns. */
+int ngdbf_server_destroy(ngdbf_server *server);
+/*
+ * ngdbf_server_pools -- device addresses of code `code_index`'s pools (any
+ * output pointer may be NULL).  The client writes y and sigma of a request's
+ * slots before committing it and reads its outputs once poll has reported it.
+ */
+int ngdbf_server_pools(ngdbf_server *server, int32_t code_index, float **y,
+                       float **sigma, uint8_t **bits, int32_t **iters,
+                       uint8_t **converged);
+/*
+ * ngdbf_server_admit -- reserve a contiguous slot range for each request, in
+ * order, stopping at the first one whose pool has no free range of its size
+ * (admission by free HBM).  Host arrays [n_requests]: code_index, n_frames
+ * (1 .. pool size), seed, frame_base in; tickets, first_slots out for the
+ * admitted prefix of *n_admitted requests.  A request larger than its pool is
+ * NGDBF_EINVAL.
+ */
+int ngdbf_server_admit(ngdbf_server *server, int32_t n_requests,
+                       const int32_t *code_index, const int64_t *n_frames,
+                       const uint64_t *seed, const uint64_t *frame_base,
+                       uint64_t *tickets, int64_t *first_slots,
+                       int32_t *n_admitted);
+/*
+ * ngdbf_server_commit -- the admitted requests' inputs are complete once the
+ * work queued so far on `stream` has run; their launch waits for it.
+ */
+int ngdbf_server_commit(ngdbf_server *server, int32_t n, const uint64_t *tickets,
+                        void *stream);
+/*
+ * ngdbf_server_pump -- queue every committed request: per code, up to
+ * max_requests_per_launch of them in one segmented launch on the next library
+ * stream, while launch staging is free (64 launches in flight at most; the
+ * rest wait for a later pump).  Never blocks on the device.
+ */
+int ngdbf_server_pump(ngdbf_server *server, int32_t *n_launched);
+/*
+ * ngdbf_server_poll -- non-blocking: writes to tickets[0 .. *n_done) the
+ * requests whose launch has finished, in launch order, at most `capacity`.
+ */
+int ngdbf_server_poll(ngdbf_server *server, int32_t capacity, uint64_t *tickets,
+                      int32_t *n_done);
+/*
+ * ngdbf_server_release -- return finished requests' slots to their pools.  The
+ * client's reads of the outputs must be complete, or queued on the stream it
+ * commits later requests on.
+ */
+int ngdbf_server_release(ngdbf_server *server, int32_t n, const uint64_t *tickets);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *ngdbf_last_error(void);
 

@@ -24,7 +24,11 @@ NGDBF_Y_I8 = 1
 #: names of the C entry points (include/ngdbf.h)
 ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "ngdbf_decode",
                  "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_code_set_shape",
-                 "ngdbf_code_get_shape", "ngdbf_autotune", "ngdbf_decode_batch", "ngdbf_last_error")
+                 "ngdbf_code_get_shape", "ngdbf_autotune", "ngdbf_decode_batch",
+                 "ngdbf_decode_segments", "ngdbf_server_create", "ngdbf_server_destroy",
+                 "ngdbf_server_pools", "ngdbf_server_admit", "ngdbf_server_commit",
+                 "ngdbf_server_pump", "ngdbf_server_poll", "ngdbf_server_release",
+                 "ngdbf_last_error")
 
 
 class NgdbfError(RuntimeError):
@@ -45,6 +49,11 @@ class ngdbf_job(ctypes.Structure):
                 ("params", ngdbf_params), ("seed", ctypes.c_uint64),
                 ("frame_base", ctypes.c_uint64), ("out_bits", ctypes.c_void_p),
                 ("out_iters", ctypes.c_void_p), ("out_converged", ctypes.c_void_p)]
+
+
+class ngdbf_segment(ctypes.Structure):
+    _fields_ = [("first_slot", ctypes.c_int64), ("frame_offset", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("frame_base", ctypes.c_uint64)]
 
 
 @dataclasses.dataclass
@@ -89,6 +98,17 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_code_get_shape.argtypes = [P, P]
         L.ngdbf_autotune.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, P, P, P]
         L.ngdbf_decode_batch.argtypes = [ctypes.POINTER(ngdbf_job), I32, P]
+        L.ngdbf_decode_segments.argtypes = [P, P, P, F, I64, ctypes.POINTER(ngdbf_params), P,
+                                            I32, I64, P, P, P, P]
+        L.ngdbf_server_create.argtypes = [I32, P, ctypes.POINTER(ngdbf_params), P, I32, I32,
+                                          ctypes.POINTER(ctypes.c_void_p)]
+        L.ngdbf_server_destroy.argtypes = [P]
+        L.ngdbf_server_pools.argtypes = [P, I32, P, P, P, P, P]
+        L.ngdbf_server_admit.argtypes = [P, I32, P, P, P, P, P, P, P]
+        L.ngdbf_server_commit.argtypes = [P, I32, P, P]
+        L.ngdbf_server_pump.argtypes = [P, P]
+        L.ngdbf_server_poll.argtypes = [P, I32, P, P]
+        L.ngdbf_server_release.argtypes = [P, I32, P]
         L.ngdbf_last_error.argtypes = []
         L.ngdbf_last_error.restype = ctypes.c_char_p
         for name in ABI_FUNCTIONS:
@@ -192,6 +212,87 @@ def ngdbf_autotune(code, y, n_frames: int, sigma, sigma_scalar: float, params: n
 def ngdbf_decode_batch(jobs, stream) -> None:
     arr = (ngdbf_job * len(jobs))(*jobs)
     _check(lib().ngdbf_decode_batch(arr, len(jobs), _stream(stream)))
+
+
+def ngdbf_decode_segments(code, y_pool, sigma_pool, sigma_scalar: float, pool_frames: int,
+                          params: ngdbf_params, segments, n_segments: int, n_frames: int,
+                          bits_pool, iters_pool, conv_pool, stream) -> None:
+    _check(lib().ngdbf_decode_segments(code, _addr(y_pool), _addr(sigma_pool), sigma_scalar,
+                                       pool_frames, ctypes.byref(params), _addr(segments),
+                                       n_segments, n_frames, _addr(bits_pool),
+                                       _addr(iters_pool), _addr(conv_pool), _stream(stream)))
+
+
+def ngdbf_server_create(codes, params, pool_frames, n_streams: int,
+                        max_requests_per_launch: int) -> ctypes.c_void_p:
+    k = len(codes)
+    c_codes = (ctypes.c_void_p * k)(*[c.value if isinstance(c, ctypes.c_void_p) else c
+                                      for c in codes])
+    c_params = (ngdbf_params * k)(*params)
+    c_pool = (ctypes.c_int64 * k)(*pool_frames)
+    out = ctypes.c_void_p()
+    _check(lib().ngdbf_server_create(k, c_codes, c_params, c_pool, n_streams,
+                                     max_requests_per_launch, ctypes.byref(out)))
+    return out
+
+
+def ngdbf_server_destroy(server) -> None:
+    _check(lib().ngdbf_server_destroy(server))
+
+
+def ngdbf_server_pools(server, code_index: int):
+    """(y, sigma, bits, iters, converged) device addresses of one code's pool."""
+    ptrs = [ctypes.c_void_p() for _ in range(5)]
+    _check(lib().ngdbf_server_pools(server, code_index, *[ctypes.byref(q) for q in ptrs]))
+    return tuple(q.value for q in ptrs)
+
+
+def ngdbf_server_admit(server, code_index, n_frames, seed, frame_base):
+    """Admit requests in order while their pools have room.
+
+    Returns (tickets, first_slots) of the admitted prefix."""
+    import numpy as np
+
+    k = len(code_index)
+    ci = np.ascontiguousarray(code_index, dtype=np.int32)
+    nf = np.ascontiguousarray(n_frames, dtype=np.int64)
+    sd = np.ascontiguousarray(seed, dtype=np.uint64)
+    fb = np.ascontiguousarray(frame_base, dtype=np.uint64)
+    tickets = np.zeros(k, dtype=np.uint64)
+    first = np.zeros(k, dtype=np.int64)
+    n_adm = ctypes.c_int32()
+    _check(lib().ngdbf_server_admit(server, k, _addr(ci), _addr(nf), _addr(sd), _addr(fb),
+                                    _addr(tickets), _addr(first), ctypes.byref(n_adm)))
+    return tickets[:n_adm.value], first[:n_adm.value]
+
+
+def ngdbf_server_commit(server, tickets, stream) -> None:
+    import numpy as np
+
+    t = np.ascontiguousarray(tickets, dtype=np.uint64)
+    _check(lib().ngdbf_server_commit(server, len(t), _addr(t), _stream(stream)))
+
+
+def ngdbf_server_pump(server) -> int:
+    n = ctypes.c_int32()
+    _check(lib().ngdbf_server_pump(server, ctypes.byref(n)))
+    return n.value
+
+
+def ngdbf_server_poll(server, capacity: int = 1 << 16):
+    import numpy as np
+
+    t = np.zeros(capacity, dtype=np.uint64)
+    n = ctypes.c_int32()
+    _check(lib().ngdbf_server_poll(server, capacity, _addr(t), ctypes.byref(n)))
+    return t[:n.value]
+
+
+def ngdbf_server_release(server, tickets) -> None:
+    import numpy as np
+
+    t = np.ascontiguousarray(tickets, dtype=np.uint64)
+    _check(lib().ngdbf_server_release(server, len(t), _addr(t)))
 
 
 def ngdbf_last_error() -> str:
@@ -304,3 +405,74 @@ def decode(code: Code, y, sigma, params: Params, seed: int, frame_base: int = 0,
         ngdbf_decode(code.handle, y, F, sig_t, sig_s, p, seed, frame_base, out.bits, out.iters,
                      out.converged, stream)
     return out
+
+
+class Server:
+    """Continuous-batching runtime: one resident slot pool per code.
+
+    The pools are torch views of the library's device buffers; a request is
+    admitted (slots reserved), its samples and sigma written into its slots,
+    committed on a stream, launched by ``pump`` together with every other
+    committed request of its code, reported by ``poll`` and released."""
+
+    def __init__(self, codes, params, pool_frames, n_streams: int = 4,
+                 max_requests_per_launch: int = 4096):
+        import torch
+
+        self.codes = list(codes)
+        self.params = list(params)
+        self.handle = ngdbf_server_create([c.handle for c in self.codes],
+                                          [p.c(NGDBF_Y_F32) for p in self.params],
+                                          list(pool_frames), n_streams,
+                                          max_requests_per_launch)
+        self.pools = []
+        dev = torch.device("cuda", torch.cuda.current_device())
+        for i, (code, F) in enumerate(zip(self.codes, pool_frames)):
+            y, sg, b, it, cv = ngdbf_server_pools(self.handle, i)
+            self.pools.append(Outputs(_wrap(b, (F, code.nbytes_row), torch.uint8, dev),
+                                      _wrap(it, (F,), torch.int32, dev),
+                                      _wrap(cv, (F,), torch.uint8, dev)))
+            self.pools[-1].y = _wrap(y, (F, code.n), torch.float32, dev)
+            self.pools[-1].sigma = _wrap(sg, (F,), torch.float32, dev)
+
+    def admit(self, code_index, n_frames, seed, frame_base):
+        return ngdbf_server_admit(self.handle, code_index, n_frames, seed, frame_base)
+
+    def commit(self, tickets, stream=None) -> None:
+        ngdbf_server_commit(self.handle, tickets, stream)
+
+    def pump(self) -> int:
+        return ngdbf_server_pump(self.handle)
+
+    def poll(self, capacity: int = 1 << 16):
+        return ngdbf_server_poll(self.handle, capacity)
+
+    def release(self, tickets) -> None:
+        ngdbf_server_release(self.handle, tickets)
+
+    def close(self) -> None:
+        if self.handle is not None and self.handle.value:
+            ngdbf_server_destroy(self.handle)
+        self.handle = None
+        self.pools = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _DeviceBuffer:
+    """__cuda_array_interface__ view of library-owned device memory."""
+
+    def __init__(self, addr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (addr, False), "version": 3, "strides": None}
+
+
+def _wrap(addr: int, shape, dtype, device):
+    import torch
+
+    typestr = {torch.uint8: "|u1", torch.int32: "<i4", torch.float32: "<f4"}[dtype]
+    return torch.as_tensor(_DeviceBuffer(addr, shape, typestr), device=device)

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libngdbf.so")
-SOURCES = [os.path.join(HERE, "csrc", "decode.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "decode.hip"), os.path.join(HERE, "csrc", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NGDBF_ARCH", "gfx950")
 

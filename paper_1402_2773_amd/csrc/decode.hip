@@ -67,6 +67,13 @@ struct DecodeArgs {
   int32_t *out_iters;
   uint8_t *out_conv;
   uint8_t *trace;
+  // segment mode (n_segments > 0): frame f of the launch belongs to the
+  // segment s with offset_s <= f < offset_{s+1}; its data live at pool slot
+  // first_slot_s + (f - offset_s) and its noise key is (seed_s,
+  // frame_base_s + f - offset_s)
+  const ngdbf_segment *segments;
+  int32_t n_segments;
+  int64_t pool_frames;                    // slots in the pools (segment mode)
   int32_t frames_per_block;               // frame slots per workgroup
   int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
   uint32_t dc_recip;                      // ceil(2^20 / d_c) for regular codes
@@ -216,8 +223,24 @@ decode_kernel(DecodeArgs a) {
   const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
   for (int64_t f = (int64_t)blockIdx.x * a.frames_per_block + fslot; f < a.n_frames;
        f += slots_total) {
-    const uint64_t frame = a.frame_base + (uint64_t)f;
-    const float sigma_f = a.sigma ? a.sigma[f] : a.sigma_scalar;
+    int64_t fs = f;            // data slot of the frame
+    uint64_t frame = a.frame_base + (uint64_t)f;
+    uint32_t key0 = a.key0, key1 = a.key1;
+    if (a.n_segments > 0) {
+      int lo = 0, hi = a.n_segments - 1;  // last segment starting at or before f
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.segments[mid].frame_offset <= f) lo = mid; else hi = mid - 1;
+      }
+      const ngdbf_segment sg = a.segments[lo];
+      fs = sg.first_slot + (f - sg.frame_offset);
+      if (fs < 0 || fs >= a.pool_frames) continue;  // outside the pools: skipped
+      frame = sg.frame_base + (uint64_t)(f - sg.frame_offset);
+      // the segment is the same for every lane of the frame: keep the key scalar
+      key0 = __builtin_amdgcn_readfirstlane((uint32_t)sg.seed);
+      key1 = __builtin_amdgcn_readfirstlane((uint32_t)(sg.seed >> 32));
+    }
+    const float sigma_f = a.sigma ? a.sigma[fs] : a.sigma_scalar;
     const float qs = a.eta * sigma_f;  // perturbation std (Sec. III-C)
     // qs^2 * 2 ln 2 with a relative slack of 4e-5 (radius bound, squared),
     // floored at 2^-100 so that the settle test below stays strict: a margin
@@ -241,7 +264,7 @@ decode_kernel(DecodeArgs a) {
         const int k = 4 * j + b;
         float v = 0.0f;
         if (j < nq && k < n) {
-          v = saturate(load_sample<YFMT>(a.y, f * (int64_t)n + k), a.ymax);
+          v = saturate(load_sample<YFMT>(a.y, fs * (int64_t)n + k), a.ymax);
           if (!REG) dg |= (uint32_t)(tab.col_ptr[k + 1] - tab.col_ptr[k]) << (4 * b);
         }
         yv[4 * r + b] = v;
@@ -313,7 +336,7 @@ decode_kernel(DecodeArgs a) {
         // their thresholds are -inf, so nothing of theirs is ever listed
         const int jc = j < nq ? j : nq - 1;
         const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
-                                        (uint32_t)(frame >> 32), a.key0, a.key1);
+                                        (uint32_t)(frame >> 32), key0, key1);
         const uint32_t u4 = uw[jc];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -451,12 +474,12 @@ decode_kernel(DecodeArgs a) {
       if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
     }
     frame_sync<WPF>();
-    uint8_t *ob = a.out_bits + (size_t)f * (size_t)nbytes;
+    uint8_t *ob = a.out_bits + (size_t)fs * (size_t)nbytes;
     const uint8_t *xb = (const uint8_t *)xw;
     for (int bb = ft; bb < nbytes; bb += FT) ob[bb] = xb[bb];
     if (ft == 0) {
-      a.out_iters[f] = t;
-      if (a.out_conv) a.out_conv[f] = (uint8_t)converged;
+      a.out_iters[fs] = t;
+      if (a.out_conv) a.out_conv[fs] = (uint8_t)converged;
     }
     frame_sync<WPF>();  // the slot is cleared for the next frame
   }
@@ -520,6 +543,18 @@ int ok() {
   g_err[0] = '\0';
   return NGDBF_OK;
 }
+
+}  // namespace
+
+namespace ngdbf_host {
+// message of a failed call of another translation unit (the server runtime)
+int set_error(int code, const char *msg) {
+  snprintf(g_err, sizeof g_err, "%s", msg);
+  return code;
+}
+}  // namespace ngdbf_host
+
+namespace {
 
 // ---------------------------------------------------------------- devices
 
@@ -685,7 +720,8 @@ struct Prepared {
 int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
             float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
             uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
-            const Shape *force, Prepared *out) {
+            const Shape *force, Prepared *out, const ngdbf_segment *segments = nullptr,
+            int32_t n_segments = 0, int64_t pool_frames = -1) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   int rc = check_params(p);
   if (rc) return rc;
@@ -735,6 +771,9 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.out_iters = out_iters;
   a.out_conv = out_conv;
   a.trace = trace;
+  a.segments = segments;
+  a.n_segments = n_segments;
+  a.pool_frames = pool_frames >= 0 ? pool_frames : n_frames;
   a.frames_per_block = sh.fpb;
   a.sw_words = (m + 31) / 32;
   a.uw_words = (n + 3) / 4;
@@ -940,6 +979,23 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t see
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "probe launch failed: %s", hipGetErrorString(e));
   return ok();
+}
+
+int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool, const float *sigma_pool,
+                          float sigma_scalar, int64_t pool_frames, const ngdbf_params *params,
+                          const ngdbf_segment *segments, int32_t n_segments, int64_t n_frames,
+                          uint8_t *bits_pool, int32_t *iters_pool, uint8_t *conv_pool,
+                          void *stream) {
+  if (n_frames > 0 && (n_segments < 1 || !segments))
+    return fail(NGDBF_EINVAL, "segments are required");
+  if (pool_frames < 0) return fail(NGDBF_EINVAL, "pool_frames < 0");
+  Prepared pr;
+  int rc = prepare(code, y_pool, n_frames, sigma_pool, sigma_scalar, params, 0, 0, bits_pool,
+                   iters_pool, conv_pool, nullptr, nullptr, &pr, segments, n_segments, pool_frames);
+  if (rc) return rc;
+  rc = pending_error();
+  if (rc) return rc;
+  return enqueue(pr, (hipStream_t)stream);
 }
 
 int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quads_per_lane,

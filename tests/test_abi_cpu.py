@@ -84,3 +84,24 @@ def test_batch_and_shape_reject_bad_arguments(L):
     bad = ng.ngdbf_job(None, None, 0, None, 0.5, p, 1, 0, None, None, None)
     with pytest.raises(ng.NgdbfError, match="job 0: code is NULL"):
         ng.ngdbf_decode_batch([bad], 0)
+
+
+def test_server_rejects_bad_arguments(L):
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    with pytest.raises(ng.NgdbfError, match="codes, params and pool sizes"):
+        ng.ngdbf_server_create([], [], [], 1, 16)
+    with pytest.raises(ng.NgdbfError, match="n_streams"):
+        ng.ngdbf_server_create([None], [p], [16], 0, 16)
+    with pytest.raises(ng.NgdbfError, match="max_requests_per_launch"):
+        ng.ngdbf_server_create([None], [p], [16], 1, 0)
+    for call in (lambda: ng.ngdbf_server_pump(None), lambda: ng.ngdbf_server_poll(None, 4),
+                 lambda: ng.ngdbf_server_release(None, [1]), lambda: ng.ngdbf_server_commit(None, [1], 0),
+                 lambda: ng.ngdbf_server_pools(None, 0)):
+        with pytest.raises(ng.NgdbfError):
+            call()
+
+
+def test_segments_require_a_table(L):
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    with pytest.raises(ng.NgdbfError, match="segments are required"):
+        ng.ngdbf_decode_segments(None, None, None, 0.5, 8, p, None, 0, 4, None, None, None, 0)
