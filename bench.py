@@ -79,6 +79,31 @@ MIX4 = [("C96", 1 << 21, _plain(100)), ("C1008", 1 << 20, _heur(3.5)),
 VALU_OPS_PER_BIT_ITER = 10 + 32.5 + 10
 
 
+def kernel_sources_digest() -> str:
+    """sha256 over the decoder's device sources (what a counter profile was taken of)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("decode.hip", "noise.h"):
+        with open(os.path.join(ROOT, "paper_1402_2773_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    profile of this workload, scaled by the same counters' reading for a plain
+    1 GiB copy; None if there is none or the kernel has changed since."""
+    path = os.path.join(ROOT, "profiles", f"decode_kernel_{workload}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_sources_sha256") != kernel_sources_digest():
+        return None
+    return d
+
+
 def algorithmic_valu_ops(code, bit_iters: float) -> float:
     dc = code.nnz / code.m
     return bit_iters * (VALU_OPS_PER_BIT_ITER + (dc - 1) * code.m / code.n)
@@ -432,7 +457,9 @@ def main() -> int:
     info_gbps = frames * code.k_info / (ms_per_step / 1e3) / 1e9
 
     alu = algorithmic_valu_ops(code, bit_iters) / kernel_s / 1e12
-    hbm = frames * hbm_bytes_per_frame(code, yfmt) / kernel_s / 1e9
+    alg_bytes = frames * hbm_bytes_per_frame(code, yfmt)
+    hbm = alg_bytes / kernel_s / 1e9
+    tr = measured_traffic(args.workload) if frames == WORKLOADS[args.workload][3] else None
     result = {
         "metric": METRIC,
         "value": info_gbps,
@@ -460,7 +487,10 @@ def main() -> int:
                        "p99": float(np.percentile(step_ms, 99)),
                        "what": "one batch launch (all frames of the step)"},
         "roofline": {"bound": "alu", "achieved": alu, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": alu / PEAK_VALU_TOPS, "traffic": None,
+                     "frac": alu / PEAK_VALU_TOPS,
+                     "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+                     "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": alg_bytes,
                      "kernel": "decode_kernel", "kernel_ms": kernel_s * 1e3,
                      "hbm_achieved_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS},
     }
