@@ -245,7 +245,7 @@ def run_mix4(args) -> int:
 
 def run_serve(args) -> int:
     """Open-loop serving: Poisson request arrivals at --serve-rate req/s for
-    --serve-seconds, frames per request log-uniform in [1, 4096], code uniform
+    --serve-seconds, frames per request log-uniform in [1, --serve-max-frames], code uniform
     over the four codes, per-request Eb/N0 ~ U[2, 5] dB, decoder seed = request
     id.  The same arrival sequence is served twice by the native runtime:
     continuously batched (every committed request of a code joins one launch)
@@ -266,7 +266,8 @@ def run_serve(args) -> int:
     rng = np.random.default_rng(int(args.serve_rate) + 17)
     n_req = int(rng.poisson(args.serve_rate * args.serve_seconds))
     t_arr = np.sort(rng.uniform(0.0, args.serve_seconds, n_req))  # Poisson process
-    n_fr = np.minimum(np.exp(rng.uniform(0.0, math.log(4097.0), n_req)).astype(np.int64), 4096)
+    mf = args.serve_max_frames
+    n_fr = np.minimum(np.exp(rng.uniform(0.0, math.log(mf + 1.0), n_req)).astype(np.int64), mf)
     n_fr = np.maximum(n_fr, 1)
     code_of = rng.integers(0, len(names), n_req).astype(np.int32)
     ebn0 = rng.uniform(2.0, 5.0, n_req)
@@ -275,12 +276,16 @@ def run_serve(args) -> int:
     gen = torch.Generator(device="cuda")
     gen.manual_seed(4242)
 
-    def serve(max_per_launch: int, window: float):
-        srv = ng.Server(dcs, params, pool, n_streams=4, max_requests_per_launch=max_per_launch)
+    def serve(max_per_launch: int, per_stream: int, window: float):
+        srv = ng.Server(dcs, params, pool, n_streams=4, max_requests_per_launch=max_per_launch,
+                        launches_per_stream=per_stream)
         queues = [np.nonzero(code_of == c)[0] for c in range(len(names))]
         q_t = [t_arr[q] for q in queues]
         qpos = [0] * len(names)
-        live = {}
+        # tickets are issued consecutively: ticket -> request through an array
+        tick0 = None
+        tick2req = np.full(n_req + 16, -1, dtype=np.int64)
+        n_live = 0
         t_done = np.full(n_req, np.nan)
         launches = 0
         stream = torch.cuda.current_stream()
@@ -319,24 +324,25 @@ def run_serve(args) -> int:
                     hi = int(np.searchsorted(q_t[c], now, side="right"))
                     if hi <= lo:
                         continue
-                    idx = q[lo:min(hi, lo + 1024)]
+                    idx = q[lo:min(hi, lo + 65536)]
                     tickets, first = srv.admit(np.full(len(idx), c, np.int32), n_fr[idx], idx.astype(np.uint64),
                                                np.zeros(len(idx), np.uint64))
                     k = len(tickets)
                     if k:
                         fill(c, idx[:k], first)
                         srv.commit(tickets, stream)
-                        for tk, r in zip(tickets.tolist(), idx[:k].tolist()):
-                            live[tk] = r
+                        if tick0 is None:
+                            tick0 = int(tickets[0])
+                        tick2req[tickets.astype(np.int64) - tick0] = idx[:k]
+                        n_live += k
                         qpos[c] += k
             launches += srv.pump()
             done = srv.poll()
             if len(done):
-                tnow = time.perf_counter() - t0
-                for tk in done.tolist():
-                    t_done[live.pop(tk)] = tnow
+                t_done[tick2req[done.astype(np.int64) - tick0]] = time.perf_counter() - t0
+                n_live -= len(done)
                 srv.release(done)
-            if not open_ and not live:
+            if not open_ and n_live == 0:
                 break
         srv.close()
         ok = ~np.isnan(t_done)
@@ -352,9 +358,9 @@ def run_serve(args) -> int:
                                "p99": float(np.percentile(lat, 99)) if len(lat) else None,
                                "p99.9": float(np.percentile(lat, 99.9)) if len(lat) else None}}
 
-    batched = serve(4096, args.serve_seconds)
+    batched = serve(4096, 1, args.serve_seconds)
     print(f"# batched: {batched}", file=sys.stderr, flush=True)
-    single = serve(1, args.serve_seconds) if not args.serve_batched_only else None
+    single = serve(1, 16, args.serve_seconds) if not args.serve_batched_only else None
     result = {
         "metric": METRIC, "value": batched["info_gbps"], "unit": "Gbit/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": batched["span_s"] * 1e3, "higher_is_better": True,
@@ -362,9 +368,10 @@ def run_serve(args) -> int:
         "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN, Poisson arrivals",
         "config": {"workload": "serve", "rate_req_per_s": args.serve_rate,
                    "window_s": args.serve_seconds, "requests": n_req,
+                   "frames_per_request": f"log-uniform [1, {mf}]",
                    "offered_frames": int(n_fr.sum()), "codes": names, "pool_slots": pool,
                    "description": "continuous batching over resident slot pools, 4 codes, "
-                                  "frames/request log-uniform [1,4096], Eb/N0 ~ U[2,5] dB"},
+                                  "Eb/N0 ~ U[2,5] dB per request, decoder seed = request id"},
         "latency_ms": batched["latency_ms"], "batched": batched, "per_request_launch": single,
     }
     print(json.dumps(result), flush=True)
@@ -384,6 +391,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: arrival window")
+    ap.add_argument("--serve-max-frames", type=int, default=4096,
+                    help="serve: frames per request are log-uniform in [1, this]")
     ap.add_argument("--serve-batched-only", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (for HBM counter scaling)")

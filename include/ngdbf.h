@@ -265,12 +265,16 @@ typedef struct ngdbf_server ngdbf_server;
  *   n_streams                  : library streams the launches rotate over, [1, 16].
  *   max_requests_per_launch    : [1, 4096]; 1 gives one launch per request (the
  *                                unbatched baseline), larger values batch.
+ *   launches_per_stream        : launches in flight per stream, >= 1, with
+ *                                n_streams * launches_per_stream <= 64.  With 1,
+ *                                requests committed while every stream is busy
+ *                                wait and join the next launch of their code.
  *   out                        : receives the handle (NULL on failure).
  */
 int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes,
                         const ngdbf_params *params, const int64_t *pool_frames,
                         int32_t n_streams, int32_t max_requests_per_launch,
-                        ngdbf_server **out);
+                        int32_t launches_per_stream, ngdbf_server **out);
 /* Waits for launches in flight, then frees everything the server owns. */
 int ngdbf_server_destroy(ngdbf_server *server);
 /*
@@ -301,10 +305,11 @@ int ngdbf_server_admit(ngdbf_server *server, int32_t n_requests,
 int ngdbf_server_commit(ngdbf_server *server, int32_t n, const uint64_t *tickets,
                         void *stream);
 /*
- * ngdbf_server_pump -- queue every committed request: per code, up to
- * max_requests_per_launch of them in one segmented launch on the next library
- * stream, while launch staging is free (64 launches in flight at most; the
- * rest wait for a later pump).  Never blocks on the device.
+ * ngdbf_server_pump -- launch committed requests while a stream has room:
+ * each launch takes, from the code whose oldest committed request is oldest,
+ * up to max_requests_per_launch requests as one segmented launch on the least
+ * loaded stream.  What does not fit waits for a later pump.  Never blocks on
+ * the device.
  */
 int ngdbf_server_pump(ngdbf_server *server, int32_t *n_launched);
 /*

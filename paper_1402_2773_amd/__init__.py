@@ -100,7 +100,7 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_decode_batch.argtypes = [ctypes.POINTER(ngdbf_job), I32, P]
         L.ngdbf_decode_segments.argtypes = [P, P, P, F, I64, ctypes.POINTER(ngdbf_params), P,
                                             I32, I64, P, P, P, P]
-        L.ngdbf_server_create.argtypes = [I32, P, ctypes.POINTER(ngdbf_params), P, I32, I32,
+        L.ngdbf_server_create.argtypes = [I32, P, ctypes.POINTER(ngdbf_params), P, I32, I32, I32,
                                           ctypes.POINTER(ctypes.c_void_p)]
         L.ngdbf_server_destroy.argtypes = [P]
         L.ngdbf_server_pools.argtypes = [P, I32, P, P, P, P, P]
@@ -224,7 +224,7 @@ def ngdbf_decode_segments(code, y_pool, sigma_pool, sigma_scalar: float, pool_fr
 
 
 def ngdbf_server_create(codes, params, pool_frames, n_streams: int,
-                        max_requests_per_launch: int) -> ctypes.c_void_p:
+                        max_requests_per_launch: int, launches_per_stream: int) -> ctypes.c_void_p:
     k = len(codes)
     c_codes = (ctypes.c_void_p * k)(*[c.value if isinstance(c, ctypes.c_void_p) else c
                                       for c in codes])
@@ -232,7 +232,8 @@ def ngdbf_server_create(codes, params, pool_frames, n_streams: int,
     c_pool = (ctypes.c_int64 * k)(*pool_frames)
     out = ctypes.c_void_p()
     _check(lib().ngdbf_server_create(k, c_codes, c_params, c_pool, n_streams,
-                                     max_requests_per_launch, ctypes.byref(out)))
+                                     max_requests_per_launch, launches_per_stream,
+                                     ctypes.byref(out)))
     return out
 
 
@@ -416,7 +417,7 @@ class Server:
     committed request of its code, reported by ``poll`` and released."""
 
     def __init__(self, codes, params, pool_frames, n_streams: int = 4,
-                 max_requests_per_launch: int = 4096):
+                 max_requests_per_launch: int = 4096, launches_per_stream: int = 1):
         import torch
 
         self.codes = list(codes)
@@ -424,7 +425,7 @@ class Server:
         self.handle = ngdbf_server_create([c.handle for c in self.codes],
                                           [p.c(NGDBF_Y_F32) for p in self.params],
                                           list(pool_frames), n_streams,
-                                          max_requests_per_launch)
+                                          max_requests_per_launch, launches_per_stream)
         self.pools = []
         dev = torch.device("cuda", torch.cuda.current_device())
         for i, (code, F) in enumerate(zip(self.codes, pool_frames)):

@@ -106,6 +106,7 @@ struct LaunchSlot {
   ngdbf_segment *dev = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  int stream = -1;  // library stream of the launch in flight
   std::vector<uint64_t> tickets;
 };
 
@@ -119,13 +120,14 @@ struct ngdbf_server {
   std::mutex mu;
   std::vector<CodePool> pools;
   std::vector<hipStream_t> streams;
+  std::vector<int> stream_load;  // launches in flight per stream
   std::vector<LaunchSlot> launches;
   std::deque<int> inflight;  // launch slot indices, in launch order
   std::unordered_map<uint64_t, Request> requests;
   std::unordered_map<hipEvent_t, int> ready_refs;  // commit event -> requests not yet launched
   uint64_t next_ticket = 1;
-  size_t next_stream = 0;
   int max_per_launch = kMaxSegments;
+  int per_stream = 1;
 };
 
 namespace {
@@ -157,7 +159,8 @@ extern "C" {
 
 int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_params *params,
                         const int64_t *pool_frames, int32_t n_streams,
-                        int32_t max_requests_per_launch, ngdbf_server **out) {
+                        int32_t max_requests_per_launch, int32_t launches_per_stream,
+                        ngdbf_server **out) {
   if (!out) return sfail(NGDBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (n_codes < 1 || !codes || !params || !pool_frames)
@@ -165,8 +168,12 @@ int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_p
   if (n_streams < 1 || n_streams > 16) return sfail(NGDBF_EINVAL, "n_streams must be in [1, 16]");
   if (max_requests_per_launch < 1 || max_requests_per_launch > kMaxSegments)
     return sfail(NGDBF_EINVAL, "max_requests_per_launch must be in [1, %d]", kMaxSegments);
+  if (launches_per_stream < 1 || (int64_t)launches_per_stream * n_streams > kLaunchSlots)
+    return sfail(NGDBF_EINVAL, "launches_per_stream must be >= 1 with n_streams * launches_per_stream <= %d",
+                 kLaunchSlots);
   ngdbf_server *s = new ngdbf_server();
   s->max_per_launch = max_requests_per_launch;
+  s->per_stream = launches_per_stream;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return sfail(NGDBF_EDEVICE, "no HIP device");
@@ -208,6 +215,7 @@ int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_p
       return sfail(NGDBF_EDEVICE, "stream creation failed");
     }
     s->streams.push_back(st);
+    s->stream_load.push_back(0);
   }
   s->launches.resize(kLaunchSlots);
   for (auto &l : s->launches) {
@@ -295,57 +303,71 @@ int ngdbf_server_pump(ngdbf_server *s, int32_t *n_launched) {
   if (!s) return sfail(NGDBF_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> g(s->mu);
   int launched = 0;
-  for (size_t c = 0; c < s->pools.size(); ++c) {
-    CodePool &p = s->pools[c];
-    while (!p.ready.empty()) {
-      int slot = -1;
-      for (int l = 0; l < (int)s->launches.size(); ++l)
-        if (!s->launches[(size_t)l].busy) {
-          slot = l;
-          break;
-        }
-      if (slot < 0) break;  // every staging slot in flight: later pumps go on
-      LaunchSlot &L = s->launches[(size_t)slot];
-      L.tickets.clear();
-      hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
-      std::vector<hipEvent_t> waits;
-      int64_t frames = 0;
-      int nseg = 0;
-      while (!p.ready.empty() && nseg < s->max_per_launch) {
-        const uint64_t t = p.ready.front();
-        p.ready.pop_front();
-        Request &r = s->requests[t];
-        L.host[nseg] = ngdbf_segment{r.first, frames, r.seed, r.frame_base};
-        frames += r.count;
-        ++nseg;
-        L.tickets.push_back(t);
-        r.state = State::kLaunched;
-        if (std::find(waits.begin(), waits.end(), r.ready) == waits.end())
-          waits.push_back(r.ready);
+  for (;;) {
+    // the code whose oldest committed request was admitted first (tickets grow)
+    int c = -1;
+    for (int i = 0; i < (int)s->pools.size(); ++i) {
+      const CodePool &q = s->pools[(size_t)i];
+      if (!q.ready.empty() && (c < 0 || q.ready.front() < s->pools[(size_t)c].ready.front())) c = i;
+    }
+    if (c < 0) break;
+    // the least loaded stream with room; none: the requests wait, and grow the
+    // next launch
+    int si = -1;
+    for (int i = 0; i < (int)s->streams.size(); ++i)
+      if (s->stream_load[(size_t)i] < s->per_stream &&
+          (si < 0 || s->stream_load[(size_t)i] < s->stream_load[(size_t)si]))
+        si = i;
+    if (si < 0) break;
+    int slot = -1;
+    for (int l = 0; l < (int)s->launches.size(); ++l)
+      if (!s->launches[(size_t)l].busy) {
+        slot = l;
+        break;
       }
-      for (hipEvent_t e : waits) {
-        if (hipStreamWaitEvent(st, e, 0) != hipSuccess) return sfail(NGDBF_EDEVICE, "wait failed");
+    if (slot < 0) break;
+    CodePool &p = s->pools[(size_t)c];
+    LaunchSlot &L = s->launches[(size_t)slot];
+    L.tickets.clear();
+    hipStream_t st = s->streams[(size_t)si];
+    std::vector<hipEvent_t> waits;
+    int64_t frames = 0;
+    int nseg = 0;
+    while (!p.ready.empty() && nseg < s->max_per_launch) {
+      const uint64_t t = p.ready.front();
+      p.ready.pop_front();
+      Request &r = s->requests[t];
+      L.host[nseg] = ngdbf_segment{r.first, frames, r.seed, r.frame_base};
+      frames += r.count;
+      ++nseg;
+      L.tickets.push_back(t);
+      r.state = State::kLaunched;
+      if (std::find(waits.begin(), waits.end(), r.ready) == waits.end()) waits.push_back(r.ready);
+    }
+    for (hipEvent_t e : waits) {
+      if (hipStreamWaitEvent(st, e, 0) != hipSuccess) return sfail(NGDBF_EDEVICE, "wait failed");
+    }
+    if (hipMemcpyAsync(L.dev, L.host, sizeof(ngdbf_segment) * (size_t)nseg,
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return sfail(NGDBF_EDEVICE, "segment upload failed");
+    const int rc = ngdbf_decode_segments(p.code, p.y, p.sigma, 0.0f, p.capacity, &p.params, L.dev,
+                                         nseg, frames, p.bits, p.iters, p.conv, st);
+    if (rc) return sfail(rc, "launch failed: %s", ngdbf_last_error());
+    if (hipEventRecord(L.done, st) != hipSuccess) return sfail(NGDBF_EDEVICE, "record failed");
+    L.busy = true;
+    L.stream = si;
+    ++s->stream_load[(size_t)si];
+    s->inflight.push_back(slot);
+    ++launched;
+    // the waits are queued: drop this launch's references to commit events
+    for (uint64_t t : L.tickets) {
+      Request &r = s->requests[t];
+      auto ref = s->ready_refs.find(r.ready);
+      if (ref != s->ready_refs.end() && --ref->second == 0) {
+        (void)hipEventDestroy(ref->first);  // released once its record has completed
+        s->ready_refs.erase(ref);
       }
-      if (hipMemcpyAsync(L.dev, L.host, sizeof(ngdbf_segment) * (size_t)nseg,
-                         hipMemcpyHostToDevice, st) != hipSuccess)
-        return sfail(NGDBF_EDEVICE, "segment upload failed");
-      const int rc = ngdbf_decode_segments(p.code, p.y, p.sigma, 0.0f, p.capacity, &p.params, L.dev,
-                                           nseg, frames, p.bits, p.iters, p.conv, st);
-      if (rc) return sfail(rc, "launch failed: %s", ngdbf_last_error());
-      if (hipEventRecord(L.done, st) != hipSuccess) return sfail(NGDBF_EDEVICE, "record failed");
-      L.busy = true;
-      s->inflight.push_back(slot);
-      ++launched;
-      // the waits are queued: drop this launch's references to commit events
-      for (uint64_t t : L.tickets) {
-        Request &r = s->requests[t];
-        auto ref = s->ready_refs.find(r.ready);
-        if (ref != s->ready_refs.end() && --ref->second == 0) {
-          (void)hipEventDestroy(ref->first);  // released once its record has completed
-          s->ready_refs.erase(ref);
-        }
-        r.ready = nullptr;
-      }
+      r.ready = nullptr;
     }
   }
   if (n_launched) *n_launched = launched;
@@ -372,6 +394,8 @@ int ngdbf_server_poll(ngdbf_server *s, int32_t capacity, uint64_t *tickets, int3
     }
     L.tickets.clear();
     L.busy = false;
+    --s->stream_load[(size_t)L.stream];
+    L.stream = -1;
     it = s->inflight.erase(it);
   }
   return NGDBF_OK;

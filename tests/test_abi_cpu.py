@@ -89,11 +89,13 @@ def test_batch_and_shape_reject_bad_arguments(L):
 def test_server_rejects_bad_arguments(L):
     p = ng.Params().c(ng.NGDBF_Y_F32)
     with pytest.raises(ng.NgdbfError, match="codes, params and pool sizes"):
-        ng.ngdbf_server_create([], [], [], 1, 16)
+        ng.ngdbf_server_create([], [], [], 1, 16, 1)
     with pytest.raises(ng.NgdbfError, match="n_streams"):
-        ng.ngdbf_server_create([None], [p], [16], 0, 16)
+        ng.ngdbf_server_create([None], [p], [16], 0, 16, 1)
     with pytest.raises(ng.NgdbfError, match="max_requests_per_launch"):
-        ng.ngdbf_server_create([None], [p], [16], 1, 0)
+        ng.ngdbf_server_create([None], [p], [16], 1, 0, 1)
+    with pytest.raises(ng.NgdbfError, match="launches_per_stream"):
+        ng.ngdbf_server_create([None], [p], [16], 4, 16, 17)
     for call in (lambda: ng.ngdbf_server_pump(None), lambda: ng.ngdbf_server_poll(None, 4),
                  lambda: ng.ngdbf_server_release(None, [1]), lambda: ng.ngdbf_server_commit(None, [1], 0),
                  lambda: ng.ngdbf_server_pools(None, 0)):

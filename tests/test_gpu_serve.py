@@ -177,7 +177,7 @@ def test_server_alone_equals_mix_equals_decode(torch_dev):
         srv.close()
     # the unbatched baseline: one launch per request
     srv1 = ng.Server([dc for _, dc in code_list], [ng.Params(**p.__dict__) for p in params],
-                     [700, 700], n_streams=2, max_requests_per_launch=1)
+                     [700, 700], n_streams=2, max_requests_per_launch=1, launches_per_stream=8)
     try:
         single = _serve(torch, srv1, code_list, reqs, list(range(len(reqs))), pump_every=2)
     finally:
