@@ -35,12 +35,17 @@ class _Params(ctypes.Structure):
     _fields_ = [("w", ctypes.c_float), ("theta", ctypes.c_float),
                 ("lam", ctypes.c_float), ("eta", ctypes.c_float),
                 ("ymax", ctypes.c_float), ("t_max", ctypes.c_int32),
-                ("smooth_window", ctypes.c_int32)]
+                ("smooth_window", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("quant_bits", ctypes.c_int32), ("noise_reuse", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
 class Params:
-    """Decoder parameters, paper notation (Sec. III-B..E, IV-A)."""
+    """Decoder parameters, paper notation (Sec. III-B..E, IV-A, IV-E, V).
+
+    variant: 0 multi-bit (Step 3b), 1 single-bit argmin (Step 3a), 2 mode
+    switching; quant_bits: 0 binary32, Q > 0 the Q-bit quantized decoder;
+    noise_reuse: 1 for the shift-register chain of Sec. V-B."""
 
     w: float = 0.75
     theta: float = -0.6
@@ -49,10 +54,14 @@ class Params:
     ymax: float = 2.5
     t_max: int = 100
     smooth_window: int = 0
+    variant: int = 0
+    quant_bits: int = 0
+    noise_reuse: int = 0
 
     def c(self) -> _Params:
         return _Params(self.w, self.theta, self.lam, self.eta, self.ymax,
-                       self.t_max, self.smooth_window)
+                       self.t_max, self.smooth_window, self.variant,
+                       self.quant_bits, self.noise_reuse)
 
 
 _lib = None
@@ -88,6 +97,19 @@ def lib():
                                            ctypes.POINTER(_Params), ctypes.c_uint64,
                                            ctypes.c_uint64, P, P, P, ctypes.c_int32]
         L.ngdbf_ref_decode_f64.restype = ctypes.c_int
+        L.ngdbf_ref_quant_half.argtypes = [ctypes.c_float, ctypes.c_int32, ctypes.c_float]
+        L.ngdbf_ref_quant_half.restype = ctypes.c_float
+        L.ngdbf_ref_threshold_events.argtypes = [ctypes.c_float, ctypes.c_float,
+                                                 ctypes.c_float, ctypes.c_int32,
+                                                 ctypes.c_int32, P, P, ctypes.c_int32]
+        L.ngdbf_ref_threshold_events.restype = ctypes.c_int32
+        L.ngdbf_ref_reuse_sample.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32,
+                                             ctypes.c_uint32, ctypes.c_int32]
+        L.ngdbf_ref_reuse_sample.restype = ctypes.c_float
+        L.ngdbf_ref_objective.argtypes = [ctypes.c_int32, ctypes.c_int32, P, P, P,
+                                          ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                          P, P]
+        L.ngdbf_ref_objective.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -138,6 +160,48 @@ def noise_block(seed: int, frame: int, t: int, quad0: int, n_quads: int) -> np.n
     z = np.zeros(4 * n_quads, dtype=np.float32)
     lib().ngdbf_ref_noise_block(seed, frame, t, quad0, n_quads, _ptr(z))
     return z
+
+
+def quant_scale(q_bits: int, ymax: float) -> float:
+    """fl32(N_Q / (2 Y_max)), the quantizer's input scale."""
+    return float(np.float32(1 << q_bits) / (np.float32(2.0) * np.float32(ymax)))
+
+
+def quant_half(v: float, q_bits: int, ymax: float) -> float:
+    """g(v) of Sec. IV-E in units of half a quantization step (an odd integer)."""
+    return float(lib().ngdbf_ref_quant_half(v, q_bits, quant_scale(q_bits, ymax)))
+
+
+def threshold_events(theta: float, lam: float, ymax: float, q_bits: int, t_max: int):
+    """[(theta~_i, tau~_i)] of Sec. V-A: quantized threshold values in channel
+    units and the non-flip count at which each becomes active."""
+    cap = 64
+    vals = np.zeros(cap, dtype=np.float64)
+    taus = np.zeros(cap, dtype=np.int32)
+    k = lib().ngdbf_ref_threshold_events(theta, lam, ymax, q_bits, t_max, _ptr(vals),
+                                         _ptr(taus), cap)
+    return [(float(vals[i]), int(taus[i])) for i in range(min(k, cap))]
+
+
+def reuse_sample(seed: int, frame: int, n: int, t: int, k: int) -> float:
+    """The standard-normal sample of bit k in round t under noise reuse."""
+    return float(lib().ngdbf_ref_reuse_sample(seed, frame, n, t, k))
+
+
+def objective(code, y: np.ndarray, ymax: float, bits: np.ndarray) -> np.ndarray:
+    """int64 [F]: the GDBF objective of the decisions in bits, fixed point 2^-20."""
+    y = np.ascontiguousarray(y)
+    y_format = 1 if y.dtype == np.int8 else 0
+    bits = np.ascontiguousarray(bits, dtype=np.uint8)
+    F = y.shape[0]
+    out = np.zeros(F, dtype=np.int64)
+    rp = np.ascontiguousarray(code.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(code.col_idx, dtype=np.int32)
+    rc = lib().ngdbf_ref_objective(code.n, code.m, _ptr(rp), _ptr(ci), _ptr(y), y_format, F,
+                                   ymax, _ptr(bits), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
 
 
 @dataclasses.dataclass

@@ -265,8 +265,91 @@ static float load_y(const job *J, int64_t f, int32_t k) {
     return ((const float *)J->y)[f * n + k];
 }
 
+/* ------------------------------------------------------------------ */
+/* Quantizer (Sec. IV-E) and threshold adaptation events (Sec. V-A).  */
+/* ------------------------------------------------------------------ */
+
+float ngdbf_ref_quant_half(float v, int32_t q_bits, float c) {
+    /* g(v) = sign(v) (floor(|v| N_Q / 2Y_max) + 1/2) (2 Y_max / N_Q); the
+     * levels stop at N_Q/2 - 1 on each side (zero is not a level).  Scaled
+     * by N_Q / Y_max this is the odd integer sign(v) (2L + 1).  sign is the
+     * signum, so g(0) = 0: a zero perturbation (eta = 0) adds nothing. */
+    if (v == 0.0f) return 0.0f;
+    float top = (float)((1 << q_bits) / 2 - 1);
+    float L = floorf(fabsf(v) * c);
+    if (L > top) L = top;                    /* NaN stays NaN               */
+    float mag = 2.0f * L + 1.0f;
+    return (v < 0.0f) ? -mag : mag;
+}
+
+static float quant_scale(int32_t q_bits, float ymax) {
+    return (float)(1 << q_bits) / (2.0f * ymax);   /* fl32(N_Q / 2Y_max) */
+}
+
+int32_t ngdbf_ref_threshold_events(float theta, float lambda, float ymax,
+                                   int32_t q_bits, int32_t t_max,
+                                   double *values, int32_t *taus, int32_t cap) {
+    float c = quant_scale(q_bits, ymax);
+    float thr = theta;                       /* theta lambda^u, u = 0       */
+    float prev = 0.0f;
+    int32_t count = 0;
+    for (int32_t u = 0; u <= t_max; ++u) {
+        if (u > 0) thr = thr * lambda;
+        float lev = ngdbf_ref_quant_half(thr, q_bits, c);
+        if (u == 0 || lev != prev) {
+            if (count < cap) {
+                values[count] = (double)lev * (double)ymax / (double)(1 << q_bits);
+                taus[count] = u;
+            }
+            ++count;
+        }
+        prev = lev;
+    }
+    return count;
+}
+
+/* ------------------------------------------------------------------ */
+/* Shift-register noise reuse (Sec. V-B).                             */
+/* ------------------------------------------------------------------ */
+
+float ngdbf_ref_reuse_sample(uint64_t seed, uint64_t frame, int32_t n,
+                             uint32_t t, int32_t k) {
+    /* One new sample enters bit 0 each round and every register passes its
+     * sample to the next bit: q_k(t) = q_{k-1}(t-1).  With the registers
+     * preloaded from the stream r (bit k holds r[n-1-k] at t = 0), bit k
+     * holds r[n-1+t-k] in round t. */
+    uint32_t j = (uint32_t)(n - 1) + t - (uint32_t)k;
+    float z4[4];
+    ngdbf_ref_noise_quad(seed, frame, 0xFFFFFFFFu, j >> 2, z4);
+    return z4[j & 3];
+}
+
+/* ------------------------------------------------------------------ */
+/* Objective function (Sec. III-B) in exact fixed point.              */
+/* ------------------------------------------------------------------ */
+
+static int64_t fixed_sample(float v) {
+    float a = v * 0x1p20f;                   /* exact unless it overflows   */
+    if (!(a == a)) a = 0.0f;
+    if (a > 0x1p40f) a = 0x1p40f;
+    if (a < -0x1p40f) a = -0x1p40f;
+    return (int64_t)rintf(a);                /* round half to even          */
+}
+
+static int64_t objective_fixed(const int *x, const float *yk, const int *s,
+                               int32_t n, int32_t m) {
+    int64_t F = 0;
+    for (int32_t k = 0; k < n; ++k) F += (int64_t)x[k] * fixed_sample(yk[k]);
+    for (int32_t i = 0; i < m; ++i) F += (int64_t)s[i] * ((int64_t)1 << 20);
+    return F;
+}
+
+/* ------------------------------------------------------------------ */
+/* FP32 / quantized decoder, one frame.                               */
+/* ------------------------------------------------------------------ */
+
 static void decode_frame_f32(const job *J, int64_t f, int *x, int *s,
-                             float *yk, float *thr, int *X, int *flip) {
+                             float *yk, float *thr, int *X, int *flip, float *E) {
     const ref_code *h = J->h;
     const ngdbf_ref_params *p = &J->p;
     int32_t n = h->n, m = h->m, T = p->t_max, W = p->smooth_window;
@@ -275,6 +358,12 @@ static void decode_frame_f32(const job *J, int64_t f, int *x, int *s,
     float sigma = J->sigma ? J->sigma[f] : J->sigma_scalar;
     float qscale = p->eta * sigma;           /* std of q_k is eta*sigma   */
     uint8_t *trace = J->trace ? J->trace + (size_t)f * (size_t)T * nb : NULL;
+    int Q = p->quant_bits;
+    float qc = Q ? quant_scale(Q, p->ymax) : 0.0f;
+    /* quantized weight w~ = g(w), in half-step units (Sec. IV-E) */
+    float wq = Q ? ngdbf_ref_quant_half(p->w, Q, qc) : 0.0f;
+    int mu = 1;                              /* mode switching (Sec. III-B) */
+    int64_t f_prev = 0;
 
     /* Step 0 and x(0) = sign(y): saturate at Y_max, x_k = -1 iff y_k < 0 */
     for (int32_t k = 0; k < n; ++k) {
@@ -302,6 +391,12 @@ static void decode_frame_f32(const job *J, int64_t f, int *x, int *s,
         /* Sec. III-E: X_k accumulates x_k(t) over t = T-W .. T */
         if (W > 0 && t >= T - W)
             for (int32_t k = 0; k < n; ++k) X[k] += x[k];
+        /* mode switching: mu drops to 0 for good once f(x(t)) < f(x(t-1)) */
+        if (p->variant == 2) {
+            int64_t fx = objective_fixed(x, yk, s, n, m);
+            if (t > 0 && fx < f_prev) mu = 0;
+            f_prev = fx;
+        }
         if (!unsatisfied) {
             pack_bits_from_x(x, n, J->out_bits + (size_t)f * nb);
             J->out_iters[f] = t;
@@ -316,27 +411,57 @@ static void decode_frame_f32(const job *J, int64_t f, int *x, int *s,
             if (J->out_conv) J->out_conv[f] = 0;
             return;
         }
-        /* Step 2: E_k = x_k y_k + w sum_{i in M(k)} s_i + q_k,
-         * evaluated as fmaf(qscale, z_k, fmaf(w, S_k, x_k*y_k)). */
+        /* Step 2: E_k = x_k y_k + w sum_{i in M(k)} s_i + q_k.
+         * Binary32: fmaf(qscale, z_k, fmaf(w, S_k, x_k*y_k)).
+         * Quantized: x_k g(y_k) + g(w) S_k + g(qscale z_k) in half steps,
+         * small integers, so the float sum is exact. */
         for (int32_t k = 0; k < n; ++k) {
             int S = 0;
             for (int32_t e = h->col_ptr[k]; e < h->col_ptr[k + 1]; ++e)
                 S += s[h->row_idx[e]];
-            float xy = (float)x[k] * yk[k];
-            float a = fmaf(p->w, (float)S, xy);
-            float z4[4];
-            ngdbf_ref_noise_quad(J->seed, frame, (uint32_t)t, (uint32_t)k >> 2, z4);
-            float E = fmaf(qscale, z4[k & 3], a);
-            /* Step 3b: flip iff E_k < theta_k */
-            flip[k] = E < thr[k];
+            float z;
+            if (p->noise_reuse) {
+                z = ngdbf_ref_reuse_sample(J->seed, frame, n, (uint32_t)t, k);
+            } else {
+                float z4[4];
+                ngdbf_ref_noise_quad(J->seed, frame, (uint32_t)t, (uint32_t)k >> 2, z4);
+                z = z4[k & 3];
+            }
+            if (Q) {
+                float Y = ngdbf_ref_quant_half(yk[k], Q, qc);
+                float qk = ngdbf_ref_quant_half(qscale * z, Q, qc);
+                E[k] = (float)x[k] * Y + wq * (float)S + qk;
+            } else {
+                float xy = (float)x[k] * yk[k];
+                float a = fmaf(p->w, (float)S, xy);
+                E[k] = fmaf(qscale, z, a);
+            }
+        }
+        /* Step 3 */
+        int multi = (p->variant == 0) || (p->variant == 2 && mu == 1);
+        if (multi) {
+            /* 3b: flip iff E_k < theta_k (quantized: g(theta_k)) */
+            for (int32_t k = 0; k < n; ++k) {
+                float th = Q ? ngdbf_ref_quant_half(thr[k], Q, qc) : thr[k];
+                flip[k] = E[k] < th;
+            }
+        } else {
+            /* 3a: flip the single bit of least E_k; ties go to the lowest
+             * index, NaN values are never chosen */
+            int32_t best = -1;
+            for (int32_t k = 0; k < n; ++k) {
+                flip[k] = 0;
+                if (E[k] == E[k] && (best < 0 || E[k] < E[best])) best = k;
+            }
+            if (best >= 0) flip[best] = 1;
         }
         /* all symbols update simultaneously from x(t) */
         for (int32_t k = 0; k < n; ++k) {
             if (flip[k]) {
                 x[k] = -x[k];
                 if (trace) trace[(size_t)t * nb + (k >> 3)] |= (uint8_t)(1u << (k & 7));
-            } else {
-                thr[k] = thr[k] * p->lambda;     /* Sec. III-D */
+            } else if (multi) {
+                thr[k] = thr[k] * p->lambda;     /* Sec. III-D, V-A */
             }
         }
     }
@@ -437,14 +562,15 @@ static void *worker_main(void *vp) {
     double *td = (double *)malloc((size_t)n * sizeof(double));
     float *yf = (float *)malloc((size_t)n * sizeof(float));
     float *tf = (float *)malloc((size_t)n * sizeof(float));
-    if (x && s && X && flip && yd && td && yf && tf) {
+    float *Ef = (float *)malloc((size_t)n * sizeof(float));
+    if (x && s && X && flip && yd && td && yf && tf && Ef) {
         int32_t nt = J->n_threads > 1 ? J->n_threads : 1;
         for (int64_t f = wa->worker; f < J->n_frames; f += nt) {
             if (J->use_f64) decode_frame_f64(J, f, x, s, yd, td, X, flip);
-            else decode_frame_f32(J, f, x, s, yf, tf, X, flip);
+            else decode_frame_f32(J, f, x, s, yf, tf, X, flip, Ef);
         }
     }
-    free(x); free(s); free(X); free(flip); free(yd); free(td); free(yf); free(tf);
+    free(x); free(s); free(X); free(flip); free(yd); free(td); free(yf); free(tf); free(Ef);
     return NULL;
 }
 
@@ -474,7 +600,51 @@ static int run_job(job *J) {
 static int check_params(const ngdbf_ref_params *p) {
     if (!p) return -1;
     if (p->t_max < 0 || p->smooth_window < 0) return -1;
+    if (p->variant < 0 || p->variant > 2) return -1;
+    if (p->noise_reuse != 0 && p->noise_reuse != 1) return -1;
+    if (p->quant_bits < 0 || p->quant_bits > 8) return -1;
+    if (p->quant_bits && !(p->ymax > 0.0f)) return -1;   /* g needs Y_max  */
+    if (p->quant_bits && p->variant == 2) return -1;     /* f is binary32  */
     return 0;
+}
+
+int ngdbf_ref_objective(int32_t n, int32_t m, const int32_t *row_ptr,
+                        const int32_t *col_idx, const void *y, int32_t y_format,
+                        int64_t n_frames, float ymax, const uint8_t *bits,
+                        int64_t *out) {
+    if (n_frames < 0 || (y_format != 0 && y_format != 1)) return -1;
+    if (n_frames > 0 && (!y || !bits || !out)) return -1;
+    ref_code h;
+    memset(&h, 0, sizeof h);
+    if (build_code(&h, n, m, row_ptr, col_idx)) { free_code(&h); return -1; }
+    int *x = (int *)malloc((size_t)n * sizeof(int));
+    int *s = (int *)malloc((size_t)m * sizeof(int));
+    float *yk = (float *)malloc((size_t)n * sizeof(float));
+    int rc = (x && s && yk) ? 0 : -1;
+    ngdbf_ref_params p0;
+    memset(&p0, 0, sizeof p0);
+    job J = {&h, y, y_format, NULL, 0.0f, p0, 0, 0, NULL, NULL, NULL, NULL, n_frames, 1, 0};
+    int32_t nb = (n + 7) / 8;
+    for (int64_t f = 0; rc == 0 && f < n_frames; ++f) {
+        for (int32_t k = 0; k < n; ++k) {
+            float v = load_y(&J, f, k);
+            if (ymax > 0.0f) {
+                if (v < -ymax) v = -ymax;
+                if (v > ymax) v = ymax;
+            }
+            yk[k] = v;
+            x[k] = ((bits[(size_t)f * nb + (k >> 3)] >> (k & 7)) & 1u) ? -1 : 1;
+        }
+        for (int32_t i = 0; i < m; ++i) {
+            int prod = 1;
+            for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) prod *= x[col_idx[e]];
+            s[i] = prod;
+        }
+        out[f] = objective_fixed(x, yk, s, n, m);
+    }
+    free(x); free(s); free(yk);
+    free_code(&h);
+    return rc;
 }
 
 int ngdbf_ref_decode(int32_t n, int32_t m, const int32_t *row_ptr,
@@ -507,6 +677,8 @@ int ngdbf_ref_decode_f64(int32_t n, int32_t m, const int32_t *row_ptr,
                          uint8_t *out_bits, int32_t *out_iters,
                          uint8_t *out_conv, int32_t n_threads) {
     if (check_params(p) || n_frames < 0) return -1;
+    /* the binary64 decoder covers the multi-bit binary32 algorithm only */
+    if (p->variant || p->quant_bits || p->noise_reuse) return -1;
     if (n_frames > 0 && (!y || !out_bits || !out_iters)) return -1;
     ref_code h;
     memset(&h, 0, sizeof h);

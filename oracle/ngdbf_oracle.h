@@ -34,6 +34,15 @@ typedef struct {
     int32_t t_max;       /* iteration limit T (Step 4)                          */
     int32_t smooth_window; /* 0: off; W > 0: output sign(X_k) with X summed
                               over t = T-W .. T if T is reached (III-E)        */
+    int32_t variant;     /* 0: multi-bit flips E_k < theta_k (Step 3b);
+                            1: single-bit flip of argmin E_k (Step 3a);
+                            2: mode switching: Step 3b until the objective
+                               f(x) first decreases, Step 3a after (III-B)    */
+    int32_t quant_bits;  /* 0: binary32 arithmetic; Q in [1, 8]: y, w, q_k and
+                            theta_k through the Q-bit quantizer g (IV-E, V-A)  */
+    int32_t noise_reuse; /* 0: a fresh q_k per bit and round; 1: one new sample
+                            per round passed along a shift-register chain,
+                            q_k(t) = q_{k-1}(t-1) (V-B)                        */
 } ngdbf_ref_params;
 
 /* Philox4x32-10 block function: out = philox(ctr, key). */
@@ -64,7 +73,7 @@ void ngdbf_ref_noise_block(uint64_t seed, uint64_t frame, uint32_t t,
 void ngdbf_ref_rho_range(uint32_t m0, uint32_t count, float *out);
 void ngdbf_ref_sincos_range(uint32_t i0, uint32_t count, float *c, float *s);
 
-/* Decode n_frames frames with the FP32 decoder.
+/* Decode n_frames frames with the FP32 (or quantized) decoder.
  *   H: n columns (bits), m rows (checks), CSR row_ptr[m+1], col_idx[nnz].
  *   y: frames x n, float32 (y_format 0) or int8 codes y_q with y = y_q/16
  *      (y_format 1), row-major.
@@ -84,6 +93,37 @@ int ngdbf_ref_decode(int32_t n, int32_t m, const int32_t *row_ptr,
                      uint64_t frame_base, uint8_t *out_bits,
                      int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
                      int32_t n_threads);
+
+/* The quantizer of Sec. IV-E in units of half a quantization step:
+ * g(v) * N_Q / Y_max = sign(v) (2L + 1), L = min(floor(|v| c), N_Q/2 - 1),
+ * c = fl32(N_Q / (2 Y_max)), N_Q = 2^Q.  sign is the signum: g(0) = 0
+ * (a zero perturbation adds nothing); NaN gives NaN. */
+float ngdbf_ref_quant_half(float v, int32_t q_bits, float c);
+
+/* Threshold adaptation events of Sec. V-A for the quantized decoder: the
+ * thresholds theta_k(u) = g(theta lambda^u), u = 0 .. t_max, with theta
+ * lambda^u formed by repeated binary32 multiplication; event i is the first
+ * u = tau_i at which the quantized value changes (tau_0 = 0).  Writes at most
+ * cap events (value in channel units, tau) and returns their number. */
+int32_t ngdbf_ref_threshold_events(float theta, float lambda, float ymax,
+                                   int32_t q_bits, int32_t t_max,
+                                   double *values, int32_t *taus, int32_t cap);
+
+/* The standard-normal sample that the shift-register chain of Sec. V-B puts
+ * at bit k in round t: element n - 1 + t - k of the frame's sample stream,
+ * whose element j is draw j & 3 of quad j >> 2 under iteration word
+ * 0xFFFFFFFF (a value no round index takes). */
+float ngdbf_ref_reuse_sample(uint64_t seed, uint64_t frame, int32_t n,
+                             uint32_t t, int32_t k);
+
+/* GDBF objective of Sec. III-B, f(x) = sum_k x_k y_k + sum_i s_i, in fixed
+ * point: F = sum_k x_k Y_k + 2^20 sum_i s_i with Y_k = rint(2^20 y_k) (y_k
+ * saturated at ymax as in decoding, clamped to +-2^40; NaN counts 0), exact
+ * in int64.  x is given as packed decoded bits (frames x ceil(n/8)). */
+int ngdbf_ref_objective(int32_t n, int32_t m, const int32_t *row_ptr,
+                        const int32_t *col_idx, const void *y, int32_t y_format,
+                        int64_t n_frames, float ymax, const uint8_t *bits,
+                        int64_t *out);
 
 /* Same algorithm in binary64 arithmetic, with the Gaussian draws formed in
  * double from the same Philox words (statistical comparison only; this is

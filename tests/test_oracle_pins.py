@@ -23,7 +23,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def _params(d):
     return oracle.Params(w=d["w"], theta=d["theta"], lam=d["lam"], eta=d["eta"],
-                         ymax=d["ymax"], t_max=d["t_max"], smooth_window=d["smooth_window"])
+                         ymax=d["ymax"], t_max=d["t_max"], smooth_window=d["smooth_window"],
+                         variant=d.get("variant", 0), quant_bits=d.get("quant_bits", 0),
+                         noise_reuse=d.get("noise_reuse", 0))
 
 
 # ---------------------------------------------------------------- worked examples
