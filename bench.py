@@ -84,7 +84,7 @@ def kernel_sources_digest() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("decode.hip", "noise.h"):
+    for f in ("decode.hip", "kernel.h", "noise.h"):
         with open(os.path.join(ROOT, "paper_1402_2773_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()

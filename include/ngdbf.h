@@ -56,7 +56,15 @@ typedef struct ngdbf_code ngdbf_code;
 #define NGDBF_Y_F32 0        /* float32 samples                               */
 #define NGDBF_Y_I8 1         /* int8 codes y_q; the decoder uses y = y_q/16    */
 
-/* Decoder parameters (paper notation; Sec. III-B..E, IV-A). */
+/* Bit-flip rules (Sec. III-B Step 3) */
+#define NGDBF_MULTI 0        /* flip every bit with E_k < theta_k (Step 3b)     */
+#define NGDBF_SINGLE 1       /* flip the one bit of least E_k, ties to the
+                                lowest index (Step 3a): S-NGDBF, S-GDBF         */
+#define NGDBF_MODE_SWITCH 2  /* Step 3b until the objective f(x) = sum x_k y_k +
+                                sum s_i first decreases from one round to the
+                                next, Step 3a from then on (mode switching)     */
+
+/* Decoder parameters (paper notation; Sec. III-B..E, IV-A, IV-E, V-A, V-B). */
 typedef struct {
     float w;              /* syndrome weight w > 0 (Sec. III-C Step 2)          */
     float theta;          /* initial threshold theta (Step 0 / 3b), finite      */
@@ -66,6 +74,22 @@ typedef struct {
     int32_t t_max;        /* iteration limit T, 0 <= T <= 65535 (Step 4)         */
     int32_t smooth_window;/* 0 = off; W > 0: smoothing over t = T-W .. T (III-E) */
     int32_t y_format;     /* NGDBF_Y_F32 or NGDBF_Y_I8                           */
+    int32_t variant;      /* NGDBF_MULTI, NGDBF_SINGLE or NGDBF_MODE_SWITCH      */
+    int32_t quant_bits;   /* 0: binary32 arithmetic.  Q in [1, 8]: the quantized
+                             decoder of Sec. IV-E: y_k, w, q_k and theta_k pass
+                             through g(v) = sign(v) (floor(|v| N_Q / 2Y_max) +
+                             1/2) 2Y_max / N_Q, N_Q = 2^Q (levels capped at
+                             N_Q/2 - 1, g(0) = 0), thresholds theta_k(u_k) =
+                             g(theta lambda^u_k) with u_k the non-flip count
+                             (Sec. V-A).  Needs ymax > 0; not with mode
+                             switching.                                         */
+    int32_t noise_reuse;  /* 0: a fresh q_k per bit and round.  1: the shift-
+                             register chain of Sec. V-B, q_k(t) = q_{k-1}(t-1),
+                             one new sample per round: bit k takes element
+                             n - 1 + t - k of the frame's stream, whose element
+                             j is draw j & 3 of Philox quad j >> 2 under the
+                             iteration word 0xFFFFFFFF.  Needs LDS for
+                             n + T - 1 samples per frame.                       */
 } ngdbf_params;
 
 /*
@@ -324,6 +348,22 @@ int ngdbf_server_poll(ngdbf_server *server, int32_t capacity, uint64_t *tickets,
  * commits later requests on.
  */
 int ngdbf_server_release(ngdbf_server *server, int32_t n, const uint64_t *tickets);
+
+/*
+ * ngdbf_objective -- the GDBF objective of Sec. III-B, f(x) = sum_k x_k y_k +
+ * sum_i s_i, of given decisions, for the convergence error of Sec. VI
+ * (average of f(x(T)) - f(c) over frames, with c the sent codeword).
+ * Evaluated exactly in fixed point: out[f] = sum_k x_k Y_k + 2^20 sum_i s_i,
+ * Y_k = rint(2^20 y_k) with y_k saturated at ymax as in decoding (ymax <= 0:
+ * none), clamped to +-2^40, NaN counted as 0.
+ *   y         : dev [n_frames][n], float32 (y_format 0) or int8 (1, y = y_q/16).
+ *   bits      : dev [n_frames][ceil(n/8)], decisions c_k = (1 - x_k)/2 LSB first.
+ *   out       : dev int64 [n_frames].
+ * Errors: NGDBF_EINVAL (NULL code or buffers, n_frames < 0, bad y_format).
+ */
+int ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format,
+                    int64_t n_frames, float ymax, const uint8_t *bits, int64_t *out,
+                    void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *ngdbf_last_error(void);

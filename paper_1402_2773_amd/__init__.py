@@ -28,7 +28,10 @@ ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "
                  "ngdbf_decode_segments", "ngdbf_server_create", "ngdbf_server_destroy",
                  "ngdbf_server_pools", "ngdbf_server_admit", "ngdbf_server_commit",
                  "ngdbf_server_pump", "ngdbf_server_poll", "ngdbf_server_release",
-                 "ngdbf_last_error")
+                 "ngdbf_objective", "ngdbf_last_error")
+
+
+NGDBF_MULTI, NGDBF_SINGLE, NGDBF_MODE_SWITCH = 0, 1, 2
 
 
 class NgdbfError(RuntimeError):
@@ -40,7 +43,9 @@ class NgdbfError(RuntimeError):
 class ngdbf_params(ctypes.Structure):
     _fields_ = [("w", ctypes.c_float), ("theta", ctypes.c_float), ("lam", ctypes.c_float),
                 ("eta", ctypes.c_float), ("ymax", ctypes.c_float), ("t_max", ctypes.c_int32),
-                ("smooth_window", ctypes.c_int32), ("y_format", ctypes.c_int32)]
+                ("smooth_window", ctypes.c_int32), ("y_format", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("quant_bits", ctypes.c_int32),
+                ("noise_reuse", ctypes.c_int32)]
 
 
 class ngdbf_job(ctypes.Structure):
@@ -58,7 +63,11 @@ class ngdbf_segment(ctypes.Structure):
 
 @dataclasses.dataclass
 class Params:
-    """Decoder parameters in the paper's notation (Sec. III-B..E, IV-A)."""
+    """Decoder parameters in the paper's notation (Sec. III-B..E, IV-A, IV-E, V).
+
+    variant: NGDBF_MULTI, NGDBF_SINGLE or NGDBF_MODE_SWITCH; quant_bits: 0 for
+    binary32, Q for the Q-bit quantized decoder; noise_reuse: 1 for the
+    shift-register noise chain."""
 
     w: float = 0.75
     theta: float = -0.6
@@ -67,10 +76,14 @@ class Params:
     ymax: float = 2.5
     t_max: int = 100
     smooth_window: int = 0
+    variant: int = 0
+    quant_bits: int = 0
+    noise_reuse: int = 0
 
     def c(self, y_format: int) -> ngdbf_params:
         return ngdbf_params(self.w, self.theta, self.lam, self.eta, self.ymax, self.t_max,
-                            self.smooth_window, y_format)
+                            self.smooth_window, y_format, self.variant, self.quant_bits,
+                            self.noise_reuse)
 
 
 _lib = None
@@ -109,6 +122,7 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_server_pump.argtypes = [P, P]
         L.ngdbf_server_poll.argtypes = [P, I32, P, P]
         L.ngdbf_server_release.argtypes = [P, I32, P]
+        L.ngdbf_objective.argtypes = [P, P, I32, I64, F, P, P, P]
         L.ngdbf_last_error.argtypes = []
         L.ngdbf_last_error.restype = ctypes.c_char_p
         for name in ABI_FUNCTIONS:
@@ -296,6 +310,11 @@ def ngdbf_server_release(server, tickets) -> None:
     _check(lib().ngdbf_server_release(server, len(t), _addr(t)))
 
 
+def ngdbf_objective(code, y, y_format: int, n_frames: int, ymax: float, bits, out, stream) -> None:
+    _check(lib().ngdbf_objective(code, _addr(y), y_format, n_frames, ymax, _addr(bits),
+                                 _addr(out), _stream(stream)))
+
+
 def ngdbf_last_error() -> str:
     return lib().ngdbf_last_error().decode()
 
@@ -477,3 +496,13 @@ def _wrap(addr: int, shape, dtype, device):
 
     typestr = {torch.uint8: "|u1", torch.int32: "<i4", torch.float32: "<f4"}[dtype]
     return torch.as_tensor(_DeviceBuffer(addr, shape, typestr), device=device)
+
+
+def objective(code: Code, y, ymax: float, bits, stream=None):
+    """int64 [F] on the device: f(x) of Sec. III-B for the decisions in bits,
+    in fixed point 2^-20 (ngdbf_objective)."""
+    import torch
+
+    out = torch.empty(y.shape[0], dtype=torch.int64, device=y.device)
+    ngdbf_objective(code.handle, y, _y_format(y), y.shape[0], ymax, bits, out, stream)
+    return out

@@ -1,0 +1,669 @@
+// kernel.h -- the NGDBF decode kernel for gfx950 (device code), shared by
+// the translation units that instantiate its variants.
+//
+// Data layout.
+//   HBM: y frame-major [F][n] (float32 or int8), sigma [F], outputs
+//        out_bits [F][ceil(n/8)], out_iters [F], out_converged [F].
+//   Code tables: uint16 N(i) (CSR) and M(k) (CSC), staged into LDS once per
+//        workgroup.
+//   LDS per frame: syndrome bits s, per-bit counts u_k of unsatisfied checks,
+//        the unsatisfied-check count, an x / flip bit row, a toggle-event list;
+//        for the extended decoders also two reduction words and, with noise
+//        reuse, the frame's sample stream.  Per wavefront a small Box-Muller
+//        work list.
+//   Registers: each lane owns QPL bit quads (bits 4j .. 4j+3) and keeps their
+//        saturated y_k, thresholds theta_k, smoothing counters and decisions.
+//
+// Frames are independent (Sec. IV): one wavefront decodes a frame of up to
+// 1024 bits with no workgroup barrier in its round loop; longer codes use
+// several wavefronts per frame.  Every round runs on chip; HBM sees y once
+// and the decoded bits once per frame.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "../../include/ngdbf.h"
+#include "noise.h"
+
+namespace ngdbf {
+
+constexpr int kWave = 64;
+// Box-Muller work-list entries per wavefront (pairs whose flip decision the
+// radius bound could not settle); past this a lane transforms its own pairs.
+constexpr int kListCap = 256;
+// a list entry: the pair's two Philox words, a_k and theta_k of both bits
+constexpr int kEntryWords = 6;
+// check-toggle events per frame and round held for the parallel u update
+constexpr int kEventCap = 256;
+// smoothing counters are 16-bit halves biased by this value
+constexpr uint32_t kXBias = 32768u;
+
+struct DecodeArgs {
+  // code tables, uint16, staged into LDS: col_idx (N(i), CSR) | row_idx
+  // (M(k), CSC) | row_ptr | col_ptr (the pointers only for irregular codes)
+  const uint32_t *tables;
+  int32_t table_words;
+  int32_t off_row, off_rowptr, off_colptr;  // uint16 offsets
+  int32_t dv, dc;                           // uniform degrees, 0 if irregular
+  int32_t n, m;
+  const void *y;
+  int64_t n_frames;
+  const float *sigma;
+  float sigma_scalar;
+  float w, theta, lambda, eta, ymax;
+  int32_t t_max, smooth_window;
+  uint32_t key0, key1;
+  uint64_t frame_base;
+  uint8_t *out_bits;
+  int32_t *out_iters;
+  uint8_t *out_conv;
+  uint8_t *trace;
+  // segment mode (n_segments > 0): frame f of the launch belongs to the
+  // segment s with offset_s <= f < offset_{s+1}; its data live at pool slot
+  // first_slot_s + (f - offset_s) and its noise key is (seed_s,
+  // frame_base_s + f - offset_s)
+  const ngdbf_segment *segments;
+  int32_t n_segments;
+  int64_t pool_frames;                    // slots in the pools (segment mode)
+  int32_t frames_per_block;               // frame slots per workgroup
+  int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
+  uint32_t dc_recip;                      // ceil(2^20 / d_c) for regular codes
+  int32_t slot_words;                     // LDS words per frame slot (even)
+  int32_t slots_off;                      // LDS word offset of the frame slots (even)
+  // extended decoders (EXT kernels)
+  int32_t variant;      // 0 multi-bit (Step 3b), 1 single-bit (Step 3a), 2 mode switching
+  int32_t quant_bits;   // 0: binary32; Q > 0: the Q-bit quantized decoder (Sec. IV-E)
+  int32_t noise_reuse;  // 1: shift-register noise chain (Sec. V-B)
+  float qc, qtop;       // quantizer scale fl32(N_Q / 2Y_max) and top level N_Q/2 - 1
+  float wq;             // g(w) in half steps
+  float qbound;         // N_Q - 1, the largest |g(q)| in half steps
+  int32_t red_off;      // slot word offset of the two 64-bit reduction words (even)
+  int32_t stream_off;   // slot word offset of the frame's sample stream
+  int32_t stream_len;   // n + T - 1 samples per frame with noise reuse
+  int32_t clear_words;  // slot words cleared per frame (the stream is rewritten)
+};
+
+template <int YFMT>
+__device__ __forceinline__ float load_sample(const void *y, int64_t idx) {
+  if (YFMT == NGDBF_Y_I8) {
+    // int8 code y_q; y = y_q / 16 exactly
+    return (float)((const int8_t *)y)[idx] * 0.0625f;
+  } else {
+    return ((const float *)y)[idx];
+  }
+}
+
+// Saturation at Y_max (Sec. IV-A); ymax <= 0 disables it.  Written as two
+// comparisons so that a NaN sample passes through unchanged.
+__device__ __forceinline__ float saturate(float v, float ymax) {
+  if (ymax > 0.0f) {
+    v = (v < -ymax) ? -ymax : v;
+    v = (v > ymax) ? ymax : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronisation of the waves that share one frame: the wave itself when a
+// single wavefront owns the frame, the workgroup (= the frame) otherwise.
+template <int WPF>
+__device__ __forceinline__ void frame_sync() {
+  if (WPF == 1) {
+    wave_sync();
+  } else {
+    __syncthreads();
+  }
+}
+
+// number of set bits of a 64-bit wave mask below this lane
+__device__ __forceinline__ uint32_t mask_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// g(v) of Sec. IV-E in units of half a quantization step, sign(v) (2L + 1)
+// with L = min(floor(|v| c), top); the signum of 0 is 0, NaN stays NaN.
+__device__ __forceinline__ float quant_half(float v, float c, float top) {
+  if (v == 0.0f) return 0.0f;
+  float L = floorf(fabsf(v) * c);
+  L = (L > top) ? top : L;
+  const float mag = 2.0f * L + 1.0f;
+  return v < 0.0f ? -mag : mag;
+}
+
+// A sample in the objective's fixed point: rint(2^20 v), clamped to
+// +-2^40, NaN counted as 0 (exact in int64).
+__device__ __forceinline__ int64_t fixed_sample(float v) {
+  float s = v * 0x1p20f;
+  s = (s == s) ? s : 0.0f;
+  s = (s > 0x1p40f) ? 0x1p40f : s;
+  s = (s < -0x1p40f) ? -0x1p40f : s;
+  return (int64_t)__builtin_rintf(s);
+}
+
+// Key of (E_k, k) for the single-bit argmin: ordered by E, then by k; -0
+// counts as +0 (they compare equal).
+__device__ __forceinline__ uint64_t argmin_key(float E, int k) {
+  uint32_t b = __float_as_uint(E == 0.0f ? 0.0f : E);
+  b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)b << 32) | (uint32_t)k;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t w = __shfl_xor(v, o);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Finish the listed pairs of one wavefront: lanes take entries in turn, draw
+// the pair's two Gaussians, and decide E_k < theta_k for both bits, with
+// E_k = fmaf(qs, z_k, a_k) (binary32) or a_k + g(qs z_k) (quantized, half
+// steps, exact); each owner then reads its two decision bits back.
+__device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t total, float qs,
+                                           uint32_t pend, uint64_t posb, uint32_t &flip,
+                                           bool quant, float qc, float qtop) {
+  wave_sync();
+  for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+    uint32_t *ent = list + kEntryWords * e;
+    float z0, z1;
+    bm_pair(ent[0], ent[1], z0, z1);
+    float E0, E1;
+    if (quant) {
+      E0 = __uint_as_float(ent[2]) + quant_half(qs * z0, qc, qtop);
+      E1 = __uint_as_float(ent[3]) + quant_half(qs * z1, qc, qtop);
+    } else {
+      E0 = __builtin_fmaf(qs, z0, __uint_as_float(ent[2]));
+      E1 = __builtin_fmaf(qs, z1, __uint_as_float(ent[3]));
+    }
+    ent[0] = (E0 < __uint_as_float(ent[4]) ? 1u : 0u) | (E1 < __uint_as_float(ent[5]) ? 2u : 0u);
+  }
+  wave_sync();
+  while (pend) {
+    const int q2 = __builtin_ctz(pend);
+    pend &= pend - 1;
+    const uint32_t ps = (uint32_t)(posb >> (8 * q2)) & 255u;
+    const uint32_t bits = list[kEntryWords * ps];
+    flip = (flip & ~(3u << (2 * q2))) | (bits << (2 * q2));
+  }
+  wave_sync();  // the list is refilled next
+}
+
+// Edges of check i (N(i)) and of bit k (M(k)) in the LDS tables.
+struct Tables {
+  const uint16_t *col_idx, *row_idx, *row_ptr, *col_ptr;
+  int dv, dc;
+  __device__ __forceinline__ int row_begin(int i) const { return dc ? i * dc : row_ptr[i]; }
+  __device__ __forceinline__ int row_end(int i) const { return dc ? i * dc + dc : row_ptr[i + 1]; }
+  __device__ __forceinline__ int col_begin(int k) const { return dv ? k * dv : col_ptr[k]; }
+  __device__ __forceinline__ int col_end(int k) const { return dv ? k * dv + dv : col_ptr[k + 1]; }
+};
+
+// Decode kernel.  WPF wavefronts cooperate on one frame; each lane owns QPL
+// bit quads j = ft + 64*WPF*r (ft = lane index within the frame).  With
+// WPF == 1 a workgroup holds several independent frames, one per wave, and
+// the round loop has no workgroup barrier.
+//
+// Per frame in LDS: s (one bit per check, 1 = unsatisfied), u_k (one byte per
+// bit: number of unsatisfied checks among M(k)), the count of unsatisfied
+// checks, and an x / flip bit row.  Per wave: the Box-Muller list.
+//
+// Round t (Sec. III-B/C/D):
+//   stop test on the unsatisfied count;
+//   for every owned bit S_k = deg_k - 2 u_k and a_k = fmaf(w, S_k, x_k y_k);
+//   one Philox call per quad; a pair of bits whose decision the bound on the
+//   Box-Muller radius settles (below) needs no transform; the others are
+//   compacted into the wave's list, transformed densely, and finished by
+//   their owners with E_k = fmaf(qs, z_k, a_k) < theta_k;
+//   each flip toggles s_i of its checks with LDS atomics, and each toggle
+//   moves u of the check's bits and the unsatisfied count by +-1.
+//
+// Exactness of the bound.  With m = (a >> 8) + 1 = f 2^e, u1 >= 2^(e-24), so
+// the radius is at most sqrt(2 (24 - e) ln 2) (the computed radius exceeds it
+// by less than 1e-7 relative), and |z| <= radius since |cos|, |sin| <= 1.
+// If a_k - theta_k >= qs * bound, every draw gives E_k >= theta_k (fma
+// rounding is monotone and theta_k is a float): no flip, and the pair needs
+// no transform.  The test runs on squares with a 4e-5 relative slack that
+// covers all rounding.  Every other pair goes through the transform.
+//
+// EXT kernels add the other decoders of the paper, switched by uniform
+// arguments: the single-bit flip of argmin E_k (Step 3a, a frame-wide
+// minimum of (E_k, k) keys), mode switching (the objective of Sec. III-B in
+// exact fixed point, summed over the frame each round until it first
+// decreases), the quantized decoder of Sec. IV-E / V-A (y, w, q_k and
+// theta_k through g, all in half-step units, so E_k is an exact small
+// integer) and the noise chain of Sec. V-B (the frame's n + T - 1 samples are
+// drawn once into LDS; bit k reads element n - 1 + t - k in round t).
+template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, bool EXT>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+decode_kernel(DecodeArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int tid = threadIdx.x;
+  const int wave = tid / kWave;
+  const int lane = tid % kWave;
+  const int fslot = wave / WPF;                // frame slot within the workgroup
+  const int ft = tid - fslot * WPF * kWave;    // lane index within the frame
+  constexpr int FT = WPF * kWave;              // lanes per frame
+  const int n = a.n, m = a.m;
+  const int nq = (n + 3) >> 2;
+  const int nbytes = (n + 7) >> 3;
+  const int T = a.t_max, W = a.smooth_window;
+
+  // stage the code tables once per workgroup
+  for (int i = tid; i < a.table_words; i += blockDim.x) lds[i] = a.tables[i];
+  const uint16_t *t16 = (const uint16_t *)lds;
+  Tables tab;
+  tab.col_idx = t16;
+  tab.row_idx = t16 + a.off_row;
+  tab.row_ptr = t16 + a.off_rowptr;
+  tab.col_ptr = t16 + a.off_colptr;
+  tab.dv = a.dv;
+  tab.dc = a.dc;
+  uint32_t *slot = lds + a.slots_off + fslot * a.slot_words;
+  uint32_t *sw = slot;                     // [sw_words] syndrome bits
+  uint32_t *uw = sw + a.sw_words;          // [uw_words] u_k bytes
+  uint32_t *xw = uw + a.uw_words;          // [xw_words] x / output bits
+  uint32_t *fw = xw + a.xw_words;          // [xw_words] flip bits (trace)
+  uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
+  uint32_t *evn = cnt + 1;                 // events listed this round
+  uint32_t *evl = evn + 1;                 // [kEventCap] toggle events
+  // EXT: [0] argmin key, [1] objective sum; the noise stream
+  uint64_t *red = (uint64_t *)(slot + a.red_off);
+  float *stream = (float *)(slot + a.stream_off);
+  uint32_t *list = lds + a.slots_off + a.frames_per_block * a.slot_words + wave * (kEntryWords * kListCap);
+  const bool quant = EXT && a.quant_bits > 0;
+  __syncthreads();
+
+  const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
+  for (int64_t f = (int64_t)blockIdx.x * a.frames_per_block + fslot; f < a.n_frames;
+       f += slots_total) {
+    int64_t fs = f;            // data slot of the frame
+    uint64_t frame = a.frame_base + (uint64_t)f;
+    uint32_t key0 = a.key0, key1 = a.key1;
+    if (a.n_segments > 0) {
+      int lo = 0, hi = a.n_segments - 1;  // last segment starting at or before f
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.segments[mid].frame_offset <= f) lo = mid; else hi = mid - 1;
+      }
+      const ngdbf_segment sg = a.segments[lo];
+      fs = sg.first_slot + (f - sg.frame_offset);
+      if (fs < 0 || fs >= a.pool_frames) continue;  // outside the pools: skipped
+      frame = sg.frame_base + (uint64_t)(f - sg.frame_offset);
+      // the segment is the same for every lane of the frame: keep the key scalar
+      key0 = __builtin_amdgcn_readfirstlane((uint32_t)sg.seed);
+      key1 = __builtin_amdgcn_readfirstlane((uint32_t)(sg.seed >> 32));
+    }
+    const float sigma_f = a.sigma ? a.sigma[fs] : a.sigma_scalar;
+    const float qs = a.eta * sigma_f;  // perturbation std (Sec. III-C)
+    // qs^2 * 2 ln 2 with a relative slack of 4e-5 (radius bound, squared),
+    // floored at 2^-100 so that the settle test below stays strict: a margin
+    // whose square underflows is never taken as settled
+    const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
+
+    if (EXT) {
+      // the argmin word starts at "no candidate"
+      for (int i = ft; i < a.clear_words; i += FT)
+        slot[i] = (i == a.red_off || i == a.red_off + 1) ? 0xFFFFFFFFu : 0u;
+      if (a.noise_reuse) {
+        // the shift-register chain (Sec. V-B): sample j of the frame's stream
+        // is draw j & 3 of quad j >> 2 under the iteration word 0xFFFFFFFF
+        const int nsq = (a.stream_len + 3) >> 2;
+        for (int jq = ft; jq < nsq; jq += FT) {
+          const Words4 wd = philox4x32_10((uint32_t)jq, 0xFFFFFFFFu, (uint32_t)frame,
+                                          (uint32_t)(frame >> 32), key0, key1);
+          float z[4];
+          bm_pair(wd.w0, wd.w1, z[0], z[1]);
+          bm_pair(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int idx = 4 * jq + b;
+            if (idx < a.stream_len) stream[idx] = quant ? quant_half(qs * z[b], a.qc, a.qtop) : z[b];
+          }
+        }
+      }
+    } else {
+      for (int i = ft; i < a.slot_words; i += FT) slot[i] = 0u;
+    }
+    frame_sync<WPF>();
+
+    // Step 0, x(0) = sign(y) with y saturated (Sec. III-A, IV-A)
+    float yv[QPL * 4], thr[QPL * 4];
+    uint32_t X2[QPL * 2];  // smoothing sums, two biased 16-bit halves each
+    uint32_t deg4[QPL];    // column degrees, one nibble per bit (irregular codes)
+    uint32_t xneg = 0;     // bit 4r+b: x_k = -1 for k = 4 j_r + b
+    uint32_t vmask = 0;    // bit 4r+b: k = 4 j_r + b is a bit of the code
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int j = ft + FT * r;
+      uint32_t nib = 0, dg = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = 4 * j + b;
+        float v = 0.0f;
+        if (j < nq && k < n) {
+          v = saturate(load_sample<YFMT>(a.y, fs * (int64_t)n + k), a.ymax);
+          if (!REG) dg |= (uint32_t)(tab.col_ptr[k + 1] - tab.col_ptr[k]) << (4 * b);
+        }
+        // quantized decoder: y~_k = g(y_k) in half steps (Sec. IV-E)
+        yv[4 * r + b] = quant ? quant_half(v, a.qc, a.qtop) : v;
+        // a bit past n gets theta = -inf: its margin is +inf, so it is settled
+        // every round, never flips and never reaches the output
+        thr[4 * r + b] = (j < nq && k < n) ? a.theta : -INFINITY;
+        vmask |= (j < nq && k < n ? 1u : 0u) << (4 * r + b);
+        nib |= (v < 0.0f ? 1u : 0u) << b;
+      }
+      X2[2 * r] = X2[2 * r + 1] = (kXBias << 16) | kXBias;
+      deg4[r] = dg;
+      xneg |= nib << (4 * r);
+      if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
+    }
+    frame_sync<WPF>();
+
+    // s(0), u(0) and the unsatisfied count from x(0)
+    uint32_t nunsat = 0;
+    for (int i = ft; i < m; i += FT) {
+      const int e0 = tab.row_begin(i), e1 = tab.row_end(i);
+      uint32_t v = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int k = tab.col_idx[e];
+        v ^= (xw[k >> 5] >> (k & 31)) & 1u;
+      }
+      if (v) {
+        atomicOr(&sw[i >> 5], 1u << (i & 31));
+        ++nunsat;
+        for (int e = e0; e < e1; ++e) {
+          const int k = tab.col_idx[e];
+          atomicAdd(&uw[k >> 2], 1u << (8 * (k & 3)));
+        }
+      }
+    }
+    if (nunsat) atomicAdd(cnt, nunsat);
+    frame_sync<WPF>();
+
+    int t = 0;
+    int converged = 0;
+    bool mu = true;        // mode switching: multi-bit rounds until f drops
+    int64_t f_prev = 0;
+    const float weff = quant ? a.wq : a.w;
+    for (;; ++t) {
+      const uint32_t unsat = *(volatile uint32_t *)cnt;
+      // smoothing window t = T-W .. T (Sec. III-E)
+      if (W > 0 && t >= T - W) {
+#pragma unroll
+        for (int q = 0; q < QPL * 4; ++q)
+          X2[q >> 1] += (((xneg >> q) & 1u) ? 0xFFFFFFFFu : 1u) << (16 * (q & 1));
+      }
+      if (EXT && a.variant == 2 && mu) {
+        // f(x(t)) = sum_k x_k y_k + sum_i s_i (Sec. III-B) in fixed point;
+        // sum_i s_i = m - 2 (unsatisfied checks)
+        int64_t part = 0;
+#pragma unroll
+        for (int q = 0; q < QPL * 4; ++q) {
+          const int64_t yf = fixed_sample(yv[q]);  // 0 past the last bit
+          part += ((xneg >> q) & 1u) ? -yf : yf;
+        }
+        part = wave_sum_i64(part);
+        if (lane == 0) atomicAdd((unsigned long long *)&red[1], (unsigned long long)part);
+        frame_sync<WPF>();
+        const int64_t fx = (int64_t)(*(volatile uint64_t *)&red[1]) +
+                           ((int64_t)m - 2 * (int64_t)unsat) * ((int64_t)1 << 20);
+        frame_sync<WPF>();
+        if (ft == 0) red[1] = 0;
+        if (t > 0 && fx < f_prev) mu = false;
+        f_prev = fx;
+      }
+      if (unsat == 0) {
+        converged = 1;
+        break;
+      }
+      if (t == T) break;
+
+      // ---- decisions for every owned bit (Steps 2, 3)
+      uint32_t flip = 0;     // bit 4r+b: flip in this round
+      const bool single = EXT && (a.variant == 1 || (a.variant == 2 && !mu));
+      if (EXT && (single || a.noise_reuse)) {
+        // every bit's E_k with its draw: from the chain (Sec. V-B) or from
+        // its own Philox quad
+        uint64_t best = ~0ull;
+#pragma unroll
+        for (int r = 0; r < QPL; ++r) {
+          const int j = ft + FT * r;
+          const int jc = j < nq ? j : nq - 1;
+          float z4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (!a.noise_reuse) {
+            const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
+                                            (uint32_t)(frame >> 32), key0, key1);
+            bm_pair(wd.w0, wd.w1, z4[0], z4[1]);
+            bm_pair(wd.w2, wd.w3, z4[2], z4[3]);
+          }
+          const uint32_t u4 = uw[jc];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int q = 4 * r + b;
+            const int k = 4 * j + b;
+            const bool valid = (vmask >> q) & 1u;
+            const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
+            const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
+            const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
+            const float av = __builtin_fmaf(weff, Sf, xy);
+            float E;
+            if (a.noise_reuse) {
+              // bit k holds element n - 1 + t - k of the stream in round t
+              const float v = valid ? stream[n - 1 + t - k] : 0.0f;
+              E = quant ? av + v : __builtin_fmaf(qs, v, av);
+            } else {
+              E = quant ? av + quant_half(qs * z4[b], a.qc, a.qtop) : __builtin_fmaf(qs, z4[b], av);
+            }
+            if (single) {
+              // Step 3a: the least E_k, ties to the lowest k, NaN never chosen
+              const uint64_t key = argmin_key(E, k);
+              if (valid && E == E && key < best) best = key;
+            } else {
+              const float th = (quant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
+              flip |= (E < th ? 1u : 0u) << q;
+            }
+          }
+        }
+        if (single) {
+          best = wave_min_u64(best);
+          if (lane == 0 && best != ~0ull) atomicMin((unsigned long long *)&red[0], (unsigned long long)best);
+          frame_sync<WPF>();
+          const uint64_t win = *(volatile uint64_t *)&red[0];
+          frame_sync<WPF>();
+          if (ft == 0) red[0] = ~0ull;
+          if (win != ~0ull) {
+            const int kb = (int)(uint32_t)win;
+            const int jb = kb >> 2;
+            if (jb % FT == ft) flip = 1u << (4 * (jb / FT) + (kb & 3));
+          }
+        }
+      } else {
+        uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
+        uint64_t posb = 0;     // list slot of each waiting pair, one byte each
+        uint32_t total = 0;    // wave-uniform list length
+  #pragma unroll
+        for (int r = 0; r < QPL; ++r) {
+          // a quad adds at most 2 * 64 entries: drain the list first if needed
+          if (r > 0 && total > (uint32_t)(kListCap - 2 * kWave)) {
+            flush_list(list, lane, total, qs, pend, posb, flip, quant, a.qc, a.qtop);
+            total = 0;
+            pend = 0;
+            posb = 0;
+          }
+          const int j = ft + FT * r;
+          // lanes past the last quad run the same code on a clamped index;
+          // their thresholds are -inf, so nothing of theirs is ever listed
+          const int jc = j < nq ? j : nq - 1;
+          const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
+                                          (uint32_t)(frame >> 32), key0, key1);
+          const uint32_t u4 = uw[jc];
+  #pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const uint32_t wa = p ? wd.w2 : wd.w0;
+            const uint32_t wb = p ? wd.w3 : wd.w1;
+            // m = (wa >> 8) + 1 = f 2^e.  clz(wa | 1) + 1 >= 24 - e (equal unless
+            // wa >> 8 is 2^i - 1 or wa < 256), so the bound is never smaller
+            const float lim = __builtin_fmaf((float)__builtin_clz(wa | 1u), bound_c, bound_c);
+            float avh[2], thh[2];
+            bool settled = true;
+  #pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int b = 2 * p + h;
+              const int q = 4 * r + b;
+              // S_k = deg_k - 2 u_k, formed exactly in binary32
+              const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
+              const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
+              // x_k y_k: flip the sign bit of y_k when x_k = -1 (exact)
+              const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
+              const float av = __builtin_fmaf(weff, Sf, xy);
+              // quantized: theta~_k = g(theta_k) (Sec. V-A); -inf stays -inf
+              const float th = (quant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
+              const float mg = av - th;
+              avh[h] = av;
+              thh[h] = th;
+              // settled without a draw: a_k - theta_k >= qs * bound (no flip);
+              // with lim > 0, mg |mg| >= lim implies mg > 0 (NaN fails the test).
+              // Quantized: |g(q_k)| <= N_Q - 1 half steps bounds every draw.
+              settled = settled && (quant ? (mg >= a.qbound) : (mg * fabsf(mg) >= lim));
+            }
+            const uint64_t bal = __ballot(!settled);
+            if (!settled) {
+              const uint32_t ps = total + mask_rank(bal);
+              const int q2 = 2 * r + p;
+              pend |= 1u << q2;
+              posb |= (uint64_t)ps << (8 * q2);
+              uint32_t *ent = list + kEntryWords * ps;
+              ent[0] = wa;
+              ent[1] = wb;
+              ent[2] = __float_as_uint(avh[0]);
+              ent[3] = __float_as_uint(avh[1]);
+              ent[4] = __float_as_uint(thh[0]);
+              ent[5] = __float_as_uint(thh[1]);
+            }
+            total += (uint32_t)__popcll(bal);
+          }
+        }
+        if (total) flush_list(list, lane, total, qs, pend, posb, flip, quant, a.qc, a.qtop);
+      }
+
+      // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
+      if (a.lambda != 1.0f && !single) {
+#pragma unroll
+        for (int q = 0; q < QPL * 4; ++q)
+          if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
+      }
+      xneg ^= flip;
+      if (TRACE) {
+#pragma unroll
+        for (int r = 0; r < QPL; ++r) {
+          const int j = ft + FT * r;
+          const uint32_t nib = (flip >> (4 * r)) & 15u;
+          if (j < nq && nib) atomicOr(&fw[j >> 3], nib << (4 * (j & 7)));
+        }
+      }
+      frame_sync<WPF>();  // every wave has read u before any toggle lands
+      // each flip toggles s_i of its checks; each toggle is an event (i, +-1)
+      // for the u of the check's bits, applied below by all lanes at once
+      uint32_t fl = flip;
+      int32_t dcnt = 0;
+      while (fl) {
+        const int q = __builtin_ctz(fl);
+        fl &= fl - 1;
+        const int k = 4 * (ft + FT * (q >> 2)) + (q & 3);
+        const int c0 = REG ? k * a.dv : tab.col_ptr[k];
+        const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
+        for (int e = c0; e < c1; ++e) {
+          const int i = tab.row_idx[e];
+          const uint32_t old = atomicXor(&sw[i >> 5], 1u << (i & 31));
+          const bool became_unsat = ((old >> (i & 31)) & 1u) == 0u;
+          dcnt += became_unsat ? 1 : -1;
+          const uint32_t ev = ((uint32_t)i << 1) | (became_unsat ? 0u : 1u);
+          const uint32_t slotn = REG ? atomicAdd(evn, 1u) : (uint32_t)kEventCap;
+          if (slotn < (uint32_t)kEventCap) {
+            evl[slotn] = ev;
+          } else {
+            // list full (or an irregular code): apply the event here
+            const uint32_t d = became_unsat ? 1u : 0xFFFFFFFFu;
+            const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
+            for (int e2 = r0; e2 < r1; ++e2) {
+              const int k2 = tab.col_idx[e2];
+              atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
+            }
+          }
+        }
+      }
+      if (dcnt) atomicAdd(cnt, (uint32_t)dcnt);
+      if (REG) {
+        frame_sync<WPF>();
+        const uint32_t nev = *(volatile uint32_t *)evn;
+        const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
+        const uint32_t nup = listed * (uint32_t)a.dc;  // one u update per lane
+        for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {
+          const uint32_t e = (x * a.dc_recip) >> 20;    // x / d_c, exact here
+          const uint32_t ev = evl[e];
+          const int i = (int)(ev >> 1);
+          const uint32_t d = (ev & 1u) ? 0xFFFFFFFFu : 1u;
+          const int k2 = tab.col_idx[i * a.dc + (int)(x - e * a.dc)];
+          atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
+        }
+        frame_sync<WPF>();
+        if (ft == 0) *evn = 0u;
+      }
+      frame_sync<WPF>();
+      if (TRACE) {
+        uint8_t *row = a.trace + ((size_t)f * (size_t)T + (size_t)t) * (size_t)nbytes;
+        const uint8_t *fb = (const uint8_t *)fw;
+        for (int bb = ft; bb < nbytes; bb += FT) row[bb] = fb[bb];
+        frame_sync<WPF>();
+        for (int i = ft; i < a.xw_words; i += FT) fw[i] = 0u;
+        frame_sync<WPF>();
+      }
+    }
+
+    // output: x, or sign(X) when T was reached with smoothing on (Sec. III-E)
+    for (int i = ft; i < a.xw_words; i += FT) xw[i] = 0u;
+    frame_sync<WPF>();
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int j = ft + FT * r;
+      uint32_t nib = (xneg >> (4 * r)) & 15u;
+      if (!converged && W > 0) {
+        nib = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const uint32_t half = (X2[2 * r + (b >> 1)] >> (16 * (b & 1))) & 0xFFFFu;
+          nib |= (half < kXBias ? 1u : 0u) << b;
+        }
+      }
+      if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
+    }
+    frame_sync<WPF>();
+    uint8_t *ob = a.out_bits + (size_t)fs * (size_t)nbytes;
+    const uint8_t *xb = (const uint8_t *)xw;
+    for (int bb = ft; bb < nbytes; bb += FT) ob[bb] = xb[bb];
+    if (ft == 0) {
+      a.out_iters[fs] = t;
+      if (a.out_conv) a.out_conv[fs] = (uint8_t)converged;
+    }
+    frame_sync<WPF>();  // the slot is cleared for the next frame
+  }
+}
+
+}  // namespace ngdbf

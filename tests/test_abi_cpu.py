@@ -69,9 +69,10 @@ def test_noise_probe_rejects_bad_ranges(L):
 
 
 def test_params_struct_layout_matches_header():
-    assert ctypes.sizeof(ng.ngdbf_params) == 32
+    assert ctypes.sizeof(ng.ngdbf_params) == 44
     names = [f[0] for f in ng.ngdbf_params._fields_]
-    assert names == ["w", "theta", "lam", "eta", "ymax", "t_max", "smooth_window", "y_format"]
+    assert names == ["w", "theta", "lam", "eta", "ymax", "t_max", "smooth_window", "y_format",
+                     "variant", "quant_bits", "noise_reuse"]
 
 
 def test_batch_and_shape_reject_bad_arguments(L):
@@ -107,3 +108,20 @@ def test_segments_require_a_table(L):
     p = ng.Params().c(ng.NGDBF_Y_F32)
     with pytest.raises(ng.NgdbfError, match="segments are required"):
         ng.ngdbf_decode_segments(None, None, None, 0.5, 8, p, None, 0, 4, None, None, None, 0)
+
+
+def test_params_validation_of_the_extended_decoders(L):
+    """Parameters are checked on the host before anything else."""
+    base = ng.Params()
+    for bad, msg in ((dict(variant=3), "unknown variant"), (dict(quant_bits=9), "quant_bits"),
+                     (dict(quant_bits=3, ymax=0.0), "finite ymax"),
+                     (dict(quant_bits=3, variant=2), "mode switching"),
+                     (dict(noise_reuse=2), "noise_reuse")):
+        p = ng.Params(**{**base.__dict__, **bad}).c(ng.NGDBF_Y_F32)
+        with pytest.raises(ng.NgdbfError, match=msg):
+            ng.ngdbf_decode(None, None, 0, None, 0.5, p, 1, 0, None, None, None, 0)
+
+
+def test_objective_rejects_bad_arguments(L):
+    with pytest.raises(ng.NgdbfError, match="code is NULL"):
+        ng.ngdbf_objective(None, None, 0, 1, 2.5, None, None, 0)
