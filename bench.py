@@ -58,6 +58,23 @@ WORKLOADS = {
                              "plain M-NGDBF, (6,32) N=2048, 4.5 dB, T=300, int8 y"),
     "c96_plain_4dB": ("C96", 4.0, _plain(100), 10000, "f32",
                       "plain M-NGDBF, (3,6) N=96, 4 dB, T=100 (10,000 frames)"),
+    # parameters of the (6,32) code from the successive-approximation search
+    "c2048_tuned_4.5dB_f32": ("C2048", 4.5, dict(w=0.162, theta=-0.287, lam=1.0, eta=0.613, ymax=2.0,
+                                                  t_max=300, smooth_window=0), 1 << 21, "f32",
+                              "plain M-NGDBF, (6,32) N=2048, 4.5 dB, T=300, searched parameters"),
+    "c2048_tuned_4.5dB_i8": ("C2048", 4.5, dict(w=0.162, theta=-0.287, lam=1.0, eta=0.613, ymax=2.0,
+                                                 t_max=300, smooth_window=0), 1 << 21, "i8",
+                             "plain M-NGDBF, (6,32) N=2048, 4.5 dB, T=300, searched parameters, int8 y"),
+    # the quantized hardware-oriented decoder of Sec. IV-E / V-A / V-B
+    "c1008_q4_reuse_sm_3.5dB": ("C1008", 3.5, dict(w=0.75, theta=-0.7, lam=0.98, eta=0.95, ymax=1.75,
+                                                    t_max=300, smooth_window=64, quant_bits=4,
+                                                    noise_reuse=1), 1 << 20, "f32",
+                                "quantized SM-NGDBF, Q=4, shift-register noise reuse, (3,6) N=1008, "
+                                "3.5 dB, T=300"),
+    # single-bit S-NGDBF (Step 3a): one flip per round
+    "c1008_s_ngdbf_3.5dB": ("C1008", 3.5, dict(w=0.75, theta=-0.6, lam=1.0, eta=1.0, ymax=2.5,
+                                                t_max=100, smooth_window=0, variant=1), 1 << 20, "f32",
+                            "S-NGDBF (single-bit argmin flip), (3,6) N=1008, 3.5 dB, T=100"),
 }
 DEFAULT = "c1008_sm_3.5dB"
 
@@ -104,9 +121,20 @@ def measured_traffic(workload: str):
     return d
 
 
-def algorithmic_valu_ops(code, bit_iters: float) -> float:
+# With noise reuse the method draws n samples to preload the chain and one
+# new sample per round; a round then costs E_k alone (10 per bit, 13 with the
+# quantized threshold g(theta_k)).
+VALU_OPS_PER_DRAW = 10 + 32.5
+
+
+def algorithmic_valu_ops(code, bit_iters: float, params=None, frames: int = 0) -> float:
     dc = code.nnz / code.m
-    return bit_iters * (VALU_OPS_PER_BIT_ITER + (dc - 1) * code.m / code.n)
+    syn = (dc - 1) * code.m / code.n
+    if params and params.get("noise_reuse"):
+        per_bit = (13 if params.get("quant_bits") else 10) + syn
+        draws = frames * code.n + bit_iters / code.n
+        return bit_iters * per_bit + draws * VALU_OPS_PER_DRAW
+    return bit_iters * (VALU_OPS_PER_BIT_ITER + syn)
 
 
 def hbm_bytes_per_frame(code, yfmt: str, per_frame_sigma: bool = False) -> int:
@@ -387,6 +415,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["mix4", "serve"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
+    ap.add_argument("--shape", default="", help="fix the launch shape: waves,quads,frames_per_block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
@@ -431,6 +460,8 @@ def main() -> int:
     sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
     seed = 2000 + int(round(ebn0 * 10))
     dev_code = ng.Code.from_ldpc(code)
+    if args.shape:
+        ng.ngdbf_code_set_shape(dev_code.handle, *[int(v) for v in args.shape.split(",")])
     y = channel.bpsk_awgn_device(frames, code.n, sigma, seed=seed)
     if yfmt == "i8":
         y = channel.quantize_int8(y)
@@ -465,10 +496,11 @@ def main() -> int:
     ms_per_step = wall / args.steps * 1e3
     info_gbps = frames * code.k_info / (ms_per_step / 1e3) / 1e9
 
-    alu = algorithmic_valu_ops(code, bit_iters) / kernel_s / 1e12
+    alu = algorithmic_valu_ops(code, bit_iters, params, frames) / kernel_s / 1e12
     alg_bytes = frames * hbm_bytes_per_frame(code, yfmt)
     hbm = alg_bytes / kernel_s / 1e9
-    tr = measured_traffic(args.workload) if frames == WORKLOADS[args.workload][3] else None
+    tr = (measured_traffic(args.workload)
+          if frames == WORKLOADS[args.workload][3] and not args.shape else None)
     result = {
         "metric": METRIC,
         "value": info_gbps,
@@ -492,6 +524,7 @@ def main() -> int:
         "ber": bit_err / (frames * code.n),
         "fer": frame_err / frames,
         "unconverged_frames": int((out.converged == 0).sum().item()),
+        "launch_shape": list(ng.ngdbf_code_get_shape(dev_code.handle, p.c(ng.NGDBF_Y_F32))),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                        "p99": float(np.percentile(step_ms, 99)),
                        "what": "one batch launch (all frames of the step)"},

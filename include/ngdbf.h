@@ -183,12 +183,16 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
  * ngdbf_code_set_shape fixes the shape used by later decodes of this code
  * (NGDBF_EINVAL if it does not fit the code, NGDBF_EUNSUPPORTED if it was not
  * built or exceeds the LDS); all-zero arguments restore the default choice.
- * ngdbf_code_get_shape reports the shape in use (host int32 [3]).
+ * ngdbf_code_get_shape reports the shape that decodes with `params` use (host
+ * int32 [3]); params may be NULL (the multi-bit binary32 decoder).  The
+ * default differs between decoders: the extended ones (quantized, noise
+ * reuse, single-bit, mode switching) take one quad per lane.
  * Not thread-safe against concurrent decodes of the same code.
  */
 int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,
                          int32_t quads_per_lane, int32_t frames_per_block);
-int ngdbf_code_get_shape(const ngdbf_code *code, int32_t shape[3]);
+int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
+                         int32_t shape[3]);
 
 /*
  * ngdbf_autotune -- time every built launch shape that fits the code on the

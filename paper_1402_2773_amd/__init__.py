@@ -108,7 +108,7 @@ def lib() -> ctypes.CDLL:
                                          U64, P, P, P, P, P]
         L.ngdbf_noise_probe.argtypes = [I32, U32, U32, U64, U64, U32, P, P, P]
         L.ngdbf_code_set_shape.argtypes = [P, I32, I32, I32]
-        L.ngdbf_code_get_shape.argtypes = [P, P]
+        L.ngdbf_code_get_shape.argtypes = [P, ctypes.POINTER(ngdbf_params), P]
         L.ngdbf_autotune.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, P, P, P]
         L.ngdbf_decode_batch.argtypes = [ctypes.POINTER(ngdbf_job), I32, P]
         L.ngdbf_decode_segments.argtypes = [P, P, P, F, I64, ctypes.POINTER(ngdbf_params), P,
@@ -207,9 +207,10 @@ def ngdbf_code_set_shape(code, waves_per_frame: int, quads_per_lane: int,
     _check(lib().ngdbf_code_set_shape(code, waves_per_frame, quads_per_lane, frames_per_block))
 
 
-def ngdbf_code_get_shape(code):
+def ngdbf_code_get_shape(code, params: Optional[ngdbf_params] = None):
     shape = (ctypes.c_int32 * 3)()
-    _check(lib().ngdbf_code_get_shape(code, shape))
+    _check(lib().ngdbf_code_get_shape(code, ctypes.byref(params) if params is not None else None,
+                                      shape))
     return tuple(shape)
 
 

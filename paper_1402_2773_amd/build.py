@@ -17,7 +17,9 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libngdbf.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("decode.hip", "decode_ext.hip", "server.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("decode.hip", "decode_ext_multi.hip", "decode_ext_single.hip",
+                     "decode_ext_switch.hip", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NGDBF_ARCH", "gfx950")
 

@@ -2,7 +2,8 @@
 // validation, the multi-bit binary32 kernels' instantiations, the noise
 // probes and the C ABI of ngdbf.h.  The kernel itself is in kernel.h; the
 // extended decoders (single-bit, mode switching, quantized, noise reuse) are
-// instantiated in decode_ext.hip.
+// instantiated in decode_ext_multi.hip, decode_ext_single.hip and
+// decode_ext_switch.hip.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -185,7 +186,10 @@ struct Layout {
   bool trace = false;   // flip-mask row per frame
   bool ext = false;     // extended decoder: two 64-bit reduction words
   int stream_len = 0;   // noise-reuse samples per frame
+  bool lists = true;    // per-wave Box-Muller lists (the settle-test path)
 };
+
+int list_words(const Layout &L) { return L.lists ? ngdbf::kEntryWords * ngdbf::kListCap : 0; }
 
 // Word offsets within one frame slot: s | u | x | flips | count | events
 // [| reductions | stream]; even, so that 64-bit LDS atomics are aligned.
@@ -203,7 +207,7 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
     w += 4;
     p.stream_off = w;
     p.clear_words = w;
-    w += L.stream_len;
+    w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
   } else {
     p.clear_words = w;
   }
@@ -215,7 +219,7 @@ int slots_offset(const ngdbf_code *c) { return (c->table_words + 1) & ~1; }
 
 size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
   return ((size_t)slots_offset(c) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
-          (size_t)(sh.block() / 64) * ngdbf::kEntryWords * ngdbf::kListCap) * 4;
+          (size_t)(sh.block() / 64) * list_words(L)) * 4;
 }
 
 bool extended(const ngdbf_params *p) {
@@ -227,6 +231,8 @@ Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
   L.trace = trace;
   L.ext = extended(p);
   L.stream_len = (p->noise_reuse && p->t_max > 0) ? c->n + p->t_max - 1 : 0;
+  // the lists serve multi-bit rounds with per-bit draws only
+  L.lists = !(p->noise_reuse || p->variant == NGDBF_SINGLE);
   return L;
 }
 
@@ -248,17 +254,22 @@ int check_shape(const ngdbf_code *c, const Shape &sh, const Layout &L) {
 }
 
 // The code's fixed shape, or the default: the fewest waves per frame, then
-// the fewest quads per lane that hold the code; eight single-wave frames per
-// workgroup, which then share one copy of the code tables.
+// the fewest quads per lane that hold the code (at most two quads per lane
+// for the extended decoders); sixteen single-wave frames per workgroup (or
+// as many as the LDS holds), which then share one copy of the code tables.
 int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
   if (c->shape[0]) {
     *out = Shape{c->shape[0], c->shape[1], c->shape[2]};
     return check_shape(c, *out, L);
   }
   const int nq = (c->n + 3) / 4;
+  // the extended decoders keep more per-bit state: at most two quads per
+  // lane (more waves per frame) keeps them out of register spills
+  const bool few_quads = L.ext;
   for (const auto &sh : kShapes) {
+    if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
     if (nq <= 64 * sh[0] * sh[1]) {
-      Shape cand{sh[0], sh[1], sh[0] == 1 ? 8 : 1};
+      Shape cand{sh[0], sh[1], sh[0] == 1 ? 16 : 1};
       while (check_shape(c, cand, L) != NGDBF_OK && cand.fpb > 1) cand.fpb /= 2;
       if (check_shape(c, cand, L) == NGDBF_OK) {
         *out = cand;
@@ -385,6 +396,8 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.stream_off = plan.stream_off;
   a.clear_words = plan.clear_words;
   a.stream_len = L.stream_len;
+  a.stream_q = (L.stream_len + 3) / 4;
+  a.list_words = list_words(L);
   a.variant = p->variant;
   a.quant_bits = p->quant_bits;
   a.noise_reuse = p->noise_reuse;
@@ -410,13 +423,20 @@ int enqueue(const Prepared &pr, hipStream_t s) {
   if (pr.a.n_frames == 0) return ok();
   const bool trace = pr.a.trace != nullptr;
   using ngdbf_host::dispatch;
-  if (pr.ext) return ngdbf_host::dispatch_ext(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
-  if (pr.y_format == NGDBF_Y_I8) {
-    return trace ? dispatch<NGDBF_Y_I8, true, false>(pr.sh, pr.a, pr.lds, pr.dev, s)
-                 : dispatch<NGDBF_Y_I8, false, false>(pr.sh, pr.a, pr.lds, pr.dev, s);
+  if (pr.ext) {
+    if (pr.a.variant == NGDBF_SINGLE)
+      return ngdbf_host::dispatch_ext_single(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
+    if (pr.a.variant == NGDBF_MODE_SWITCH)
+      return ngdbf_host::dispatch_ext_switch(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
+    return ngdbf_host::dispatch_ext_multi(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
   }
-  return trace ? dispatch<NGDBF_Y_F32, true, false>(pr.sh, pr.a, pr.lds, pr.dev, s)
-               : dispatch<NGDBF_Y_F32, false, false>(pr.sh, pr.a, pr.lds, pr.dev, s);
+  constexpr int kBase = ngdbf::kExtNone;
+  if (pr.y_format == NGDBF_Y_I8) {
+    return trace ? dispatch<NGDBF_Y_I8, true, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s)
+                 : dispatch<NGDBF_Y_I8, false, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s);
+  }
+  return trace ? dispatch<NGDBF_Y_F32, true, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s)
+               : dispatch<NGDBF_Y_F32, false, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s);
 }
 
 int pending_error() {
@@ -656,10 +676,13 @@ int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quad
   return ok();
 }
 
-int ngdbf_code_get_shape(const ngdbf_code *code, int32_t shape[3]) {
+int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params, int32_t shape[3]) {
   if (!code || !shape) return fail(NGDBF_EINVAL, "code and shape are required");
+  if (params) {
+    if (int rc = check_params(params)) return rc;
+  }
   Shape sh;
-  int rc = pick_shape(code, Layout{}, &sh);
+  int rc = pick_shape(code, params ? layout_of(code, params, false) : Layout{}, &sh);
   if (rc) return rc;
   shape[0] = sh.wpf;
   shape[1] = sh.qpl;

@@ -26,7 +26,7 @@ struct Shape {
 #define NGDBF_SHAPES(X) \
   X(1, 1) X(1, 2) X(1, 4) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(16, 1)
 
-template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, bool EXT>
+template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, int EXT>
 int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int dev, hipStream_t s) {
   auto kern = ngdbf::decode_kernel<WPF, QPL, YFMT, TRACE, REG, EXT>;
   if (lds_bytes > 64 * 1024 &&
@@ -49,7 +49,7 @@ int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int de
   return NGDBF_OK;
 }
 
-template <int YFMT, bool TRACE, bool EXT>
+template <int YFMT, bool TRACE, int EXT>
 int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, hipStream_t s) {
 #define NGDBF_CASE(W_, Q_)                                                       \
   if (sh.wpf == W_ && sh.qpl == Q_)                                              \
@@ -60,8 +60,24 @@ int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, h
   return fail(NGDBF_EUNSUPPORTED, "no kernel for %d waves x %d quads", sh.wpf, sh.qpl);
 }
 
-// The extended decoders (decode_ext.hip).
-int dispatch_ext(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, hipStream_t s,
-                 int y_format, bool trace);
+// The extended decoders, one translation unit per family
+// (decode_ext_multi.hip, decode_ext_single.hip, decode_ext_switch.hip).
+int dispatch_ext_multi(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
+                       hipStream_t s, int y_format, bool trace);
+int dispatch_ext_single(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
+                        hipStream_t s, int y_format, bool trace);
+int dispatch_ext_switch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
+                        hipStream_t s, int y_format, bool trace);
+
+// Instances of one family for every y format and trace setting.
+#define NGDBF_DISPATCH_FAMILY(NAME, EXT_)                                                    \
+  int NAME(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, hipStream_t s, \
+           int y_format, bool trace) {                                                      \
+    if (y_format == NGDBF_Y_I8)                                                             \
+      return trace ? dispatch<NGDBF_Y_I8, true, EXT_>(sh, a, lds, dev, s)                   \
+                   : dispatch<NGDBF_Y_I8, false, EXT_>(sh, a, lds, dev, s);                 \
+    return trace ? dispatch<NGDBF_Y_F32, true, EXT_>(sh, a, lds, dev, s)                    \
+                 : dispatch<NGDBF_Y_F32, false, EXT_>(sh, a, lds, dev, s);                  \
+  }
 
 }  // namespace ngdbf_host

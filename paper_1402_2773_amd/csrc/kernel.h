@@ -41,6 +41,12 @@ constexpr int kEventCap = 256;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 
+// decode_kernel's EXT argument: which decoder family the instance holds
+constexpr int kExtNone = 0;    // multi-bit, binary32, per-bit draws
+constexpr int kExtMulti = 1;   // multi-bit with quantization and/or noise reuse
+constexpr int kExtSingle = 2;  // single-bit flips (Step 3a)
+constexpr int kExtSwitch = 3;  // mode switching (Step 3b, then 3a)
+
 struct DecodeArgs {
   // code tables, uint16, staged into LDS: col_idx (N(i), CSR) | row_idx
   // (M(k), CSC) | row_ptr | col_ptr (the pointers only for irregular codes)
@@ -83,6 +89,8 @@ struct DecodeArgs {
   int32_t red_off;      // slot word offset of the two 64-bit reduction words (even)
   int32_t stream_off;   // slot word offset of the frame's sample stream
   int32_t stream_len;   // n + T - 1 samples per frame with noise reuse
+  int32_t stream_q;     // ceil(stream_len / 4): sample i sits at (i & 3) * stream_q + (i >> 2)
+  int32_t list_words;   // Box-Muller list words per wave (0 when no list is used)
   int32_t clear_words;  // slot words cleared per frame (the stream is rewritten)
 };
 
@@ -242,17 +250,20 @@ struct Tables {
 // no transform.  The test runs on squares with a 4e-5 relative slack that
 // covers all rounding.  Every other pair goes through the transform.
 //
-// EXT kernels add the other decoders of the paper, switched by uniform
-// arguments: the single-bit flip of argmin E_k (Step 3a, a frame-wide
+// EXT kernels add the other decoders of the paper (EXT = kExtMulti: the
+// multi-bit rule with quantization or noise reuse; kExtSingle: Step 3a;
+// kExtSwitch: mode switching), each with quantization and noise reuse as
+// uniform arguments: the single-bit flip of argmin E_k (Step 3a, a frame-wide
 // minimum of (E_k, k) keys), mode switching (the objective of Sec. III-B in
 // exact fixed point, summed over the frame each round until it first
 // decreases), the quantized decoder of Sec. IV-E / V-A (y, w, q_k and
 // theta_k through g, all in half-step units, so E_k is an exact small
 // integer) and the noise chain of Sec. V-B (the frame's n + T - 1 samples are
 // drawn once into LDS; bit k reads element n - 1 + t - k in round t).
-template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, bool EXT>
+template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, int EXT>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 decode_kernel(DecodeArgs a) {
+  constexpr bool X = EXT != kExtNone;
   extern __shared__ uint32_t lds[];
   const int tid = threadIdx.x;
   const int wave = tid / kWave;
@@ -286,8 +297,8 @@ decode_kernel(DecodeArgs a) {
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
-  uint32_t *list = lds + a.slots_off + a.frames_per_block * a.slot_words + wave * (kEntryWords * kListCap);
-  const bool quant = EXT && a.quant_bits > 0;
+  uint32_t *list = lds + a.slots_off + a.frames_per_block * a.slot_words + wave * a.list_words;
+  const bool quant = (EXT == kExtMulti || EXT == kExtSingle) && a.quant_bits > 0;
   __syncthreads();
 
   const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
@@ -317,7 +328,7 @@ decode_kernel(DecodeArgs a) {
     // whose square underflows is never taken as settled
     const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
 
-    if (EXT) {
+    if (X) {
       // the argmin word starts at "no candidate"
       for (int i = ft; i < a.clear_words; i += FT)
         slot[i] = (i == a.red_off || i == a.red_off + 1) ? 0xFFFFFFFFu : 0u;
@@ -334,7 +345,9 @@ decode_kernel(DecodeArgs a) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int idx = 4 * jq + b;
-            if (idx < a.stream_len) stream[idx] = quant ? quant_half(qs * z[b], a.qc, a.qtop) : z[b];
+            // four interleaved rows: the lanes of a round read consecutive words
+            if (idx < a.stream_len)
+              stream[b * a.stream_q + jq] = quant ? quant_half(qs * z[b], a.qc, a.qtop) : z[b];
           }
         }
       }
@@ -410,7 +423,7 @@ decode_kernel(DecodeArgs a) {
         for (int q = 0; q < QPL * 4; ++q)
           X2[q >> 1] += (((xneg >> q) & 1u) ? 0xFFFFFFFFu : 1u) << (16 * (q & 1));
       }
-      if (EXT && a.variant == 2 && mu) {
+      if (EXT == kExtSwitch && mu) {
         // f(x(t)) = sum_k x_k y_k + sum_i s_i (Sec. III-B) in fixed point;
         // sum_i s_i = m - 2 (unsatisfied checks)
         int64_t part = 0;
@@ -437,8 +450,8 @@ decode_kernel(DecodeArgs a) {
 
       // ---- decisions for every owned bit (Steps 2, 3)
       uint32_t flip = 0;     // bit 4r+b: flip in this round
-      const bool single = EXT && (a.variant == 1 || (a.variant == 2 && !mu));
-      if (EXT && (single || a.noise_reuse)) {
+      const bool single = EXT == kExtSingle || (EXT == kExtSwitch && !mu);
+      if (X && (single || a.noise_reuse)) {
         // every bit's E_k with its draw: from the chain (Sec. V-B) or from
         // its own Philox quad
         uint64_t best = ~0ull;
@@ -466,7 +479,8 @@ decode_kernel(DecodeArgs a) {
             float E;
             if (a.noise_reuse) {
               // bit k holds element n - 1 + t - k of the stream in round t
-              const float v = valid ? stream[n - 1 + t - k] : 0.0f;
+              const int idx = n - 1 + t - k;
+              const float v = valid ? stream[(idx & 3) * a.stream_q + (idx >> 2)] : 0.0f;
               E = quant ? av + v : __builtin_fmaf(qs, v, av);
             } else {
               E = quant ? av + quant_half(qs * z4[b], a.qc, a.qtop) : __builtin_fmaf(qs, z4[b], av);

@@ -1,0 +1,248 @@
+"""Parameter sweeps and the successive-approximation search of Sec. IV-A.
+
+Every decode goes through the library (one launch per point, or one batched
+launch over many parameter sets sharing the same received frames); only the
+error counting happens here, on the device, against the all-zero codeword
+that the synthetic channel transmits.
+
+  python -m paper_1402_2773_amd.sweep ebn0 --code C1008 --params sm --ebn0 2:5:0.5
+  python -m paper_1402_2773_amd.sweep vary --code C1008 --params sm --ebn0 3.5 --vary theta=-1.2:-0.2:0.1
+  python -m paper_1402_2773_amd.sweep search --code C2048 --params c2048 --ebn0 4.5
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import math
+import os
+import sys
+import time
+from typing import Dict, List, Optional, Sequence
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import paper_1402_2773_amd as ng  # noqa: E402
+
+
+def heuristic_params(ebn0: float) -> Dict:
+    """SM-NGDBF of Sec. IV-A: theta = -0.9, eta = 0.95, lambda by Eb/N0 (0.99
+    below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 from 4.5), w = 0.75,
+    smoothing over the last 64 rounds, T = 300."""
+    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.5 else 0.90
+    return dict(w=0.75, theta=-0.9, lam=lam, eta=0.95, ymax=2.5, t_max=300, smooth_window=64)
+
+
+def plain_params(ebn0: float) -> Dict:
+    """Non-adaptive M-NGDBF: theta = -0.6, eta = 0.9, w = 0.75, T = 300."""
+    return dict(w=0.75, theta=-0.6, lam=1.0, eta=0.9, ymax=2.5, t_max=300, smooth_window=0)
+
+
+def high_rate_params(ebn0: float) -> Dict:
+    """The (6,32) code's set: theta = -0.7, eta = 0.65, Y_max = 2.0 (the
+    paper's high-rate values), w = 0.125 (w d_v = 0.75), T = 300."""
+    return dict(w=0.125, theta=-0.7, lam=1.0, eta=0.65, ymax=2.0, t_max=300, smooth_window=0)
+
+
+def high_rate_tuned_params(ebn0: float) -> Dict:
+    """The (6,32) code's parameters found by successive_approximation at
+    4.5 dB on 2^16 frames (from the high-rate set above): w = 0.162,
+    theta = -0.287, eta = 0.613, lambda = 1, Y_max = 2.0, T = 300."""
+    return dict(w=0.162, theta=-0.287, lam=1.0, eta=0.613, ymax=2.0, t_max=300, smooth_window=0)
+
+
+PARAM_SETS = {"sm": heuristic_params, "plain": plain_params, "c2048": high_rate_params,
+              "c2048t": high_rate_tuned_params}
+
+
+@dataclasses.dataclass
+class Point:
+    code: str
+    ebn0: float
+    params: Dict
+    frames: int
+    y_format: str
+    ber: float
+    fer: float
+    avg_iterations: float
+    unconverged: int
+    kernel_ms: float
+    info_gbps: float
+    seed: int
+
+    def row(self) -> Dict:
+        return dataclasses.asdict(self)
+
+
+def _errors(torch, bits, n):
+    """Bit errors per frame against the all-zero codeword (popcount of the
+    decoded bits, padding bits are zero)."""
+    table = torch.tensor([bin(i).count("1") for i in range(256)], dtype=torch.int32,
+                         device=bits.device)
+    return table[bits.long()].sum(dim=1)
+
+
+def _channel(code, ebn0: float, frames: int, seed: int, y_format: str):
+    from synth import channel
+
+    sigma = float(channel.sigma_from_ebn0(ebn0, code.rate))
+    y = channel.bpsk_awgn_device(frames, code.n, sigma, seed=seed)
+    if y_format == "i8":
+        y = channel.quantize_int8(y)
+    import numpy as np
+
+    return y, float(np.float32(sigma))
+
+
+def run_point(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
+              y_format: str = "f32", y=None, sigma=None) -> Point:
+    """Decode `frames` frames at one Eb/N0 and count errors."""
+    import torch
+
+    if y is None:
+        y, sigma = _channel(code, ebn0, frames, seed, y_format)
+    p = ng.Params(**params)
+    out = ng.alloc_outputs(dev_code, frames, y.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    errs = _errors(torch, out.bits, code.n)
+    return Point(code=code.name, ebn0=ebn0, params=params, frames=frames, y_format=y_format,
+                 ber=float(errs.sum().item()) / (frames * code.n),
+                 fer=float((errs > 0).double().mean().item()),
+                 avg_iterations=float(out.iters.double().mean().item()),
+                 unconverged=int((out.converged == 0).sum().item()), kernel_ms=ms,
+                 info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed)
+
+
+def run_grid(code, dev_code, ebn0: float, param_list: Sequence[Dict], frames: int, seed: int,
+             y_format: str = "f32") -> List[Point]:
+    """Many parameter sets on the same received frames, as one batched launch
+    (ngdbf_decode_batch: the jobs run concurrently on library streams)."""
+    import torch
+
+    y, sigma = _channel(code, ebn0, frames, seed, y_format)
+    outs = [ng.alloc_outputs(dev_code, frames, y.device) for _ in param_list]
+    jobs = [ng.job(dev_code, y, sigma, ng.Params(**pr), seed, o) for pr, o in zip(param_list, outs)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    ng.ngdbf_decode_batch(jobs, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / max(len(param_list), 1)
+    pts = []
+    for pr, out in zip(param_list, outs):
+        errs = _errors(torch, out.bits, code.n)
+        pts.append(Point(code=code.name, ebn0=ebn0, params=dict(pr), frames=frames,
+                         y_format=y_format, ber=float(errs.sum().item()) / (frames * code.n),
+                         fer=float((errs > 0).double().mean().item()),
+                         avg_iterations=float(out.iters.double().mean().item()),
+                         unconverged=int((out.converged == 0).sum().item()), kernel_ms=ms,
+                         info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed))
+    return pts
+
+
+def _score(pt: Point):
+    # lower BER first; equal BER (e.g. zero errors): fewer iterations
+    return (pt.ber, pt.avg_iterations)
+
+
+def successive_approximation(code, dev_code, ebn0: float, start: Dict, ranges: Dict[str, tuple],
+                             frames: int, seed: int, points: int = 7, shrink: float = 0.35,
+                             steps: int = 3, passes: int = 1, log=None) -> Dict:
+    """Sec. IV-A: optimise theta, lambda, eta and w one at a time, holding the
+    others fixed; each free parameter is searched on a grid over its domain,
+    the domain shrinks around the best value, and the search repeats until
+    the step is small.  Every grid is one batched launch on the same frames."""
+    cur = dict(start)
+    for _ in range(passes):
+        for name, (lo, hi) in ranges.items():
+            a, b = lo, hi
+            for _ in range(steps):
+                vals = [a + (b - a) * i / (points - 1) for i in range(points)]
+                grid = [{**cur, name: v} for v in vals]
+                pts = run_grid(code, dev_code, ebn0, grid, frames, seed)
+                best = min(pts, key=_score)
+                cur[name] = best.params[name]
+                if log:
+                    log({"search": name, "values": vals, "ber": [p.ber for p in pts],
+                         "avg_iterations": [p.avg_iterations for p in pts], "best": cur[name]})
+                half = (b - a) * shrink / 2
+                a, b = max(lo, cur[name] - half), min(hi, cur[name] + half)
+    return cur
+
+
+def _range(spec: str) -> List[float]:
+    if ":" not in spec:
+        return [float(v) for v in spec.split(",")]
+    lo, hi, step = (float(v) for v in spec.split(":"))
+    n = int(math.floor((hi - lo) / step + 1e-9)) + 1
+    return [round(lo + i * step, 10) for i in range(n)]
+
+
+def main(argv: Optional[Sequence[str]] = None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("mode", choices=["ebn0", "vary", "search"])
+    ap.add_argument("--code", default="C1008")
+    ap.add_argument("--params", default="sm", choices=sorted(PARAM_SETS))
+    ap.add_argument("--set", action="append", default=[], help="override, e.g. t_max=100")
+    ap.add_argument("--ebn0", default="3.5")
+    ap.add_argument("--frames", type=int, default=1 << 20)
+    ap.add_argument("--y-format", default="f32", choices=["f32", "i8"])
+    ap.add_argument("--vary", default="", help="name=lo:hi:step (vary mode)")
+    ap.add_argument("--seed", type=int, default=0, help="0: 2000 + 10 * Eb/N0")
+    ap.add_argument("--out", default="", help="append JSON lines here (default stdout)")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    from synth import codes
+
+    if not torch.cuda.is_available():
+        print("the sweep needs a HIP device", file=sys.stderr)
+        return 1
+    code = codes.named_code(args.code)
+    dc = ng.Code.from_ldpc(code)
+    sink = open(args.out, "a") if args.out else sys.stdout
+
+    def emit(d):
+        sink.write(json.dumps(d) + "\n")
+        sink.flush()
+
+    def params_at(e):
+        pr = PARAM_SETS[args.params](e)
+        for kv in args.set:
+            k, v = kv.split("=")
+            pr[k] = type(pr.get(k, 0.0))(float(v)) if k in pr else int(v)
+        return pr
+
+    t0 = time.time()
+    for e in _range(args.ebn0):
+        seed = args.seed or int(2000 + round(10 * e))
+        if args.mode == "ebn0":
+            emit(run_point(code, dc, e, params_at(e), args.frames, seed, args.y_format).row())
+        elif args.mode == "vary":
+            name, spec = args.vary.split("=")
+            grid = [{**params_at(e), name: v} for v in _range(spec)]
+            for pt in run_grid(code, dc, e, grid, args.frames, seed, args.y_format):
+                emit(pt.row())
+        else:
+            ranges = {"theta": (-1.5, -0.1), "lam": (0.85, 1.0), "eta": (0.3, 1.3), "w": (0.05, 1.5)}
+            best = successive_approximation(code, dc, e, params_at(e), ranges, args.frames, seed,
+                                            log=emit)
+            emit({"code": code.name, "ebn0": e, "best_params": best})
+            emit(run_point(code, dc, e, best, args.frames, seed + 1, args.y_format).row())
+    print(f"# sweep done in {time.time() - t0:.1f} s", file=sys.stderr)
+    dc.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

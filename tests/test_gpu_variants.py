@@ -206,3 +206,24 @@ def test_objective_kernel_and_convergence_error(torch_dev):
         assert (f_max.cpu().numpy() == oracle.objective(c, yy, 2.5, np.zeros_like(r.bits))).all()
         eps = (f_out - f_max).double().mean().item() / 2.0 ** 20
         say("convergence error", eps)
+
+
+def test_full_size_quantized_reuse_sampled(torch_dev):
+    """The benchmark's quantized workload at full size (2^20 frames of C1008
+    at 3.5 dB, default launch shape): sampled frames against the oracle."""
+    torch = torch_dev
+    c, dc = dev_code("C1008")
+    F = 1 << 20
+    sig = float(np.float32(channel.sigma_from_ebn0(3.5, c.rate)))
+    p = oracle.Params(w=0.75, theta=-0.7, lam=0.98, eta=0.95, ymax=1.75, t_max=300,
+                      smooth_window=64, quant_bits=4, noise_reuse=1)
+    say("full size quantized C1008 2^20")
+    y = channel.bpsk_awgn_device(F, c.n, sig, seed=2035)
+    out = ng.decode(dc, y, sig, ng.Params(**p.__dict__), 2035)
+    torch.cuda.synchronize()
+    for start in (0, F // 2 + 5, F - 64):
+        yh = y[start:start + 64].cpu().numpy()
+        r = oracle.decode(c, yh, np.float32(sig), p, 2035, frame_base=start, threads=8)
+        g = (out.bits[start:start + 64].cpu().numpy(), out.iters[start:start + 64].cpu().numpy(),
+             out.converged[start:start + 64].cpu().numpy(), None)
+        assert_same(g, r, trace=False)
