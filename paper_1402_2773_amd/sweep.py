@@ -8,6 +8,7 @@ that the synthetic channel transmits.
   python -m paper_1402_2773_amd.sweep ebn0 --code C1008 --params sm --ebn0 2:5:0.5
   python -m paper_1402_2773_amd.sweep vary --code C1008 --params sm --ebn0 3.5 --vary theta=-1.2:-0.2:0.1
   python -m paper_1402_2773_amd.sweep search --code C2048 --params c2048 --ebn0 4.5
+  python -m paper_1402_2773_amd.sweep convergence --code C1008 --ebn0 5 --frames 100
 """
 from __future__ import annotations
 
@@ -179,6 +180,38 @@ def successive_approximation(code, dev_code, ebn0: float, start: Dict, ranges: D
     return cur
 
 
+# Sec. VI: the decoders compared by average convergence error, T = 100
+CONVERGENCE_SET = {
+    "S-GDBF": dict(w=1.0, theta=-0.6, lam=1.0, eta=0.0, ymax=2.5, t_max=100, variant=1),
+    "M-GDBF (mode switching)": dict(w=1.0, theta=-0.6, lam=1.0, eta=0.0, ymax=2.5, t_max=100,
+                                    variant=2),
+    "AT-GDBF": dict(w=1.0, theta=-0.6, lam=0.99, eta=0.0, ymax=2.5, t_max=100),
+    "S-NGDBF": dict(w=0.75, theta=-0.6, lam=1.0, eta=1.0, ymax=2.5, t_max=100, variant=1),
+    "M-NGDBF (adaptive)": dict(w=0.75, theta=-0.9, lam=0.99, eta=0.95, ymax=2.5, t_max=100),
+    "SM-NGDBF": dict(w=0.75, theta=-0.9, lam=0.99, eta=0.95, ymax=2.5, t_max=100,
+                     smooth_window=64),
+}
+
+
+def convergence_error(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int) -> Dict:
+    """Sec. VI: eps = mean over frames of f(x(T)) - f_max, with f the objective
+    of Sec. III-B evaluated by the library (ngdbf_objective) for the decoded
+    word and for the sent (all-zero) codeword."""
+    import torch
+
+    y, sigma = _channel(code, ebn0, frames, seed, "f32")
+    out = ng.decode(dev_code, y, sigma, ng.Params(**params), seed)
+    f_out = ng.objective(dev_code, y, params["ymax"], out.bits)
+    f_max = ng.objective(dev_code, y, params["ymax"], torch.zeros_like(out.bits))
+    torch.cuda.synchronize()
+    gap = (f_out - f_max).double() / 2.0 ** 20
+    errs = _errors(torch, out.bits, code.n)
+    return {"code": code.name, "ebn0": ebn0, "frames": frames, "params": params,
+            "eps": float(gap.mean().item()), "eps_std": float(gap.std().item()) if frames > 1 else 0.0,
+            "fer": float((errs > 0).double().mean().item()),
+            "avg_iterations": float(out.iters.double().mean().item()), "seed": seed}
+
+
 def _range(spec: str) -> List[float]:
     if ":" not in spec:
         return [float(v) for v in spec.split(",")]
@@ -189,7 +222,7 @@ def _range(spec: str) -> List[float]:
 
 def main(argv: Optional[Sequence[str]] = None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("mode", choices=["ebn0", "vary", "search"])
+    ap.add_argument("mode", choices=["ebn0", "vary", "search", "convergence"])
     ap.add_argument("--code", default="C1008")
     ap.add_argument("--params", default="sm", choices=sorted(PARAM_SETS))
     ap.add_argument("--set", action="append", default=[], help="override, e.g. t_max=100")
@@ -233,6 +266,9 @@ def main(argv: Optional[Sequence[str]] = None) -> int:
             grid = [{**params_at(e), name: v} for v in _range(spec)]
             for pt in run_grid(code, dc, e, grid, args.frames, seed, args.y_format):
                 emit(pt.row())
+        elif args.mode == "convergence":
+            for name, pr in CONVERGENCE_SET.items():
+                emit({"algorithm": name, **convergence_error(code, dc, e, pr, args.frames, seed)})
         else:
             ranges = {"theta": (-1.5, -0.1), "lam": (0.85, 1.0), "eta": (0.3, 1.3), "w": (0.05, 1.5)}
             best = successive_approximation(code, dc, e, params_at(e), ranges, args.frames, seed,
