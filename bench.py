@@ -78,6 +78,13 @@ WORKLOADS = {
 }
 DEFAULT = "c1008_sm_3.5dB"
 
+# launch shapes (waves per frame, quads per lane, frames per workgroup) chosen
+# by timing for workloads whose default shape is slower (timed per shape on the GPU)
+WORKLOAD_SHAPES = {
+    "c2048_plain_4.5dB_f32": (4, 2, 1), "c2048_plain_4.5dB_i8": (4, 2, 1),
+    "c2048_tuned_4.5dB_f32": (4, 2, 1), "c2048_tuned_4.5dB_i8": (4, 2, 1),
+}
+
 # Batched multi-code workload: the four codes in frame proportions 4:2:1:1,
 # per-frame Eb/N0 uniform in [2, 5] dB, per-code parameters as above
 MIX4 = [("C96", 1 << 21, _plain(100)), ("C1008", 1 << 20, _heur(3.5)),
@@ -215,12 +222,14 @@ def run_mix4(args) -> int:
 
     plain_ms, _ = timed(plain, max(1, args.steps // 2), 1)
 
-    # batched: autotuned shapes, one batch call captured into a graph
+    # batched: one batch call captured into a graph (default shapes, or the
+    # autotuner's choice on a sample with --mix-autotune)
     tuned = {}
     for it in items:
-        n_s = min(it["frames"], 1 << 17)  # several times the resident frames
-        best, ms = ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
-        tuned[it["name"]] = list(best)
+        if args.mix_autotune:
+            n_s = min(it["frames"], 1 << 17)  # several times the resident frames
+            best, ms = ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
+        tuned[it["name"]] = list(ng.ngdbf_code_get_shape(it["dc"].handle, it["p"].c(ng.NGDBF_Y_F32)))
     jobs = [ng.job(it["dc"], it["y"], it["sig"], it["p"], it["seed"], it["out"]) for it in items]
     ng.ngdbf_decode_batch(jobs, None)
     torch.cuda.synchronize()
@@ -256,7 +265,8 @@ def run_mix4(args) -> int:
         "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN, per-frame Eb/N0 ~ U[2,5] dB",
         "config": {"workload": "mix4", "codes": {k: v for k, v in per_code.items()},
                    "frames": sum(it["frames"] for it in items),
-                   "description": "one graph-captured batched launch of C96:C1008:C2048:C4000 = 4:2:1:1"},
+                   "description": "one graph-captured batched launch of C96:C1008:C2048:C4000 = 4:2:1:1",
+                   "autotuned": bool(args.mix_autotune)},
         "plain_per_code_launch": {"ms_per_step": plain_ms,
                                   "value": info_bits / (plain_ms / 1e3) / 1e9,
                                   "same_results_as_batched": same},
@@ -386,9 +396,9 @@ def run_serve(args) -> int:
                                "p99": float(np.percentile(lat, 99)) if len(lat) else None,
                                "p99.9": float(np.percentile(lat, 99.9)) if len(lat) else None}}
 
-    batched = serve(4096, 1, args.serve_seconds)
+    batched = serve(32768, 1, args.serve_seconds)
     print(f"# batched: {batched}", file=sys.stderr, flush=True)
-    single = serve(1, 16, args.serve_seconds) if not args.serve_batched_only else None
+    single = serve(1, 8, args.serve_seconds) if not args.serve_batched_only else None
     result = {
         "metric": METRIC, "value": batched["info_gbps"], "unit": "Gbit/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": batched["span_s"] * 1e3, "higher_is_better": True,
@@ -408,16 +418,66 @@ def run_serve(args) -> int:
     return 0
 
 
+def run_latency(args) -> int:
+    """Per-launch latency of the default workload's decoder for batch sizes
+    1 .. 2^16 frames: p50 / p99 of HIP-event times over repeated launches."""
+    import numpy as np
+    import torch
+
+    import paper_1402_2773_amd as ng
+    from synth import channel, codes
+
+    code_name, ebn0, params, _, _, desc = WORKLOADS[DEFAULT]
+    code = codes.named_code(code_name)
+    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
+    seed = 2000 + int(round(ebn0 * 10))
+    dc = ng.Code.from_ldpc(code)
+    p = ng.Params(**params)
+    rows = []
+    for b in [1, 4, 16, 64, 256, 1024, 4096, 16384, 65536]:
+        y = channel.bpsk_awgn_device(b, code.n, sigma, seed=seed + b)
+        out = ng.alloc_outputs(dc, b, "cuda")
+        reps = 200 if b <= 4096 else 50
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            ng.decode(dc, y, sigma, p, seed, out=out, stream=stream)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for i, (e0, e1) in enumerate(ev):
+            e0.record(stream)
+            ng.decode(dc, y, sigma, p, seed, frame_base=i * b, out=out, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        rows.append({"frames": b, "p50_ms": float(np.percentile(ms, 50)),
+                     "p99_ms": float(np.percentile(ms, 99)),
+                     "info_gbps_at_p50": b * code.k_info / (np.percentile(ms, 50) / 1e3) / 1e9})
+        print(f"# batch {b}: {rows[-1]}", file=sys.stderr, flush=True)
+    result = {
+        "metric": METRIC, "value": rows[-1]["info_gbps_at_p50"], "unit": "Gbit/s", "n_gpus": 1,
+        "steps": len(rows), "warmup": 3, "ms_per_step": rows[-1]["p50_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic: seeded (3,6) LDPC code, all-zero codeword, BPSK-AWGN",
+        "config": {"workload": "latency", "description": desc + "; one launch per batch"},
+        "latency_by_batch": rows,
+    }
+    print(json.dumps(result), flush=True)
+    dc.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) + ["mix4", "serve"])
+    ap.add_argument("--workload", default=DEFAULT,
+                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
     ap.add_argument("--shape", default="", help="fix the launch shape: waves,quads,frames_per_block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mix-autotune", action="store_true", help="mix4: autotune each code first")
     ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: arrival window")
     ap.add_argument("--serve-max-frames", type=int, default=4096,
@@ -453,6 +513,8 @@ def main() -> int:
         return run_mix4(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "latency":
+        return run_latency(args)
     code_name, ebn0, params, frames, yfmt, desc = WORKLOADS[args.workload]
     if args.frames:
         frames = args.frames
@@ -462,6 +524,8 @@ def main() -> int:
     dev_code = ng.Code.from_ldpc(code)
     if args.shape:
         ng.ngdbf_code_set_shape(dev_code.handle, *[int(v) for v in args.shape.split(",")])
+    elif args.workload in WORKLOAD_SHAPES:
+        ng.ngdbf_code_set_shape(dev_code.handle, *WORKLOAD_SHAPES[args.workload])
     y = channel.bpsk_awgn_device(frames, code.n, sigma, seed=seed)
     if yfmt == "i8":
         y = channel.quantize_int8(y)

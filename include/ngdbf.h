@@ -228,10 +228,12 @@ typedef struct {
 /*
  * ngdbf_decode_batch -- decode several jobs (frames of different codes,
  * parameters and SNRs, Sec. III for each) as one unit of work on `stream`:
- * the jobs run concurrently on library-owned streams forked from and joined
- * back to `stream` with events, so the whole batch is one node group when
- * the caller captures `stream` into a hipGraph.  Every job is validated
- * before any work is queued.  Results equal those of ngdbf_decode per job.
+ * jobs of fewer than 65536 frames run concurrently on library-owned streams
+ * forked from and joined back to `stream` with events; larger jobs, each of
+ * which fills the device, run one after another on `stream` beside them.  The
+ * whole batch is one node group when the caller captures `stream` into a
+ * hipGraph.  Every job is validated before any work is queued.  Results equal
+ * those of ngdbf_decode per job.
  * jobs: host array [n_jobs]; all codes on the current device.
  * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0), NGDBF_EDEVICE.
  */
@@ -291,10 +293,10 @@ typedef struct ngdbf_server ngdbf_server;
  *   codes, params, pool_frames : host arrays [n_codes]; params[i].y_format must
  *                                be NGDBF_Y_F32; the codes must outlive the server.
  *   n_streams                  : library streams the launches rotate over, [1, 16].
- *   max_requests_per_launch    : [1, 4096]; 1 gives one launch per request (the
+ *   max_requests_per_launch    : [1, 32768]; 1 gives one launch per request (the
  *                                unbatched baseline), larger values batch.
  *   launches_per_stream        : launches in flight per stream, >= 1, with
- *                                n_streams * launches_per_stream <= 64.  With 1,
+ *                                n_streams * launches_per_stream <= 32.  With 1,
  *                                requests committed while every stream is busy
  *                                wait and join the next launch of their code.
  *   out                        : receives the handle (NULL on failure).

@@ -437,7 +437,7 @@ class Server:
     committed request of its code, reported by ``poll`` and released."""
 
     def __init__(self, codes, params, pool_frames, n_streams: int = 4,
-                 max_requests_per_launch: int = 4096, launches_per_stream: int = 1):
+                 max_requests_per_launch: int = 32768, launches_per_stream: int = 1):
         import torch
 
         self.codes = list(codes)

@@ -787,9 +787,23 @@ int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   if (n_jobs == 0) return ok();
   if (n_jobs == 1) return enqueue(prs[0], s);
+  // A job of kFullJob frames or more fills the device by itself (its
+  // persistent grid is the resident capacity): such jobs run one after another
+  // on `stream`; the smaller ones run concurrently beside them on library
+  // streams, forked from and joined back to `stream`.
+  constexpr int64_t kFullJob = 65536;
+  std::vector<int> small, large;
+  for (int i = 0; i < n_jobs; ++i) (prs[i].a.n_frames >= kFullJob ? large : small).push_back(i);
+  if (small.empty()) {
+    for (int i : large) {
+      rc = enqueue(prs[i], s);
+      if (rc) return rc;
+    }
+    return ok();
+  }
   DeviceState &ds = device_state(prs[0].dev);
   std::lock_guard<std::mutex> g(ds.mu);
-  const size_t lanes = (size_t)std::min(n_jobs, 8);
+  const size_t lanes = std::min(small.size(), (size_t)8);
   while (ds.streams.size() < lanes) {
     hipStream_t ns = nullptr;
     hipEvent_t ne = nullptr;
@@ -807,10 +821,9 @@ int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
   for (size_t l = 0; l < lanes; ++l)
     if (hipStreamWaitEvent(ds.streams[l], ds.fork, 0) != hipSuccess)
       return fail(NGDBF_EDEVICE, "fork wait failed");
-  for (int i = 0; i < n_jobs; ++i) {
-    rc = enqueue(prs[i], ds.streams[(size_t)i % lanes]);
-    if (rc) break;
-  }
+  for (size_t q = 0; q < small.size() && !rc; ++q)
+    rc = enqueue(prs[(size_t)small[q]], ds.streams[q % lanes]);
+  for (size_t q = 0; q < large.size() && !rc; ++q) rc = enqueue(prs[(size_t)large[q]], s);
   // join: `stream` waits for every library stream (also after a failure, so
   // that the fork/join structure stays balanced under graph capture)
   for (size_t l = 0; l < lanes; ++l) {

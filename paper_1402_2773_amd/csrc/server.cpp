@@ -110,8 +110,8 @@ struct LaunchSlot {
   std::vector<uint64_t> tickets;
 };
 
-constexpr int kMaxSegments = 4096;  // requests per launch
-constexpr int kLaunchSlots = 64;    // launches in flight
+constexpr int kMaxSegments = 32768;  // requests per launch
+constexpr int kLaunchSlots = 32;     // launches in flight
 
 }  // namespace
 

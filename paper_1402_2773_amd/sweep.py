@@ -72,9 +72,38 @@ class Point:
     kernel_ms: float
     info_gbps: float
     seed: int
+    fer_ci95: tuple = (0.0, 0.0)        # Wilson interval of the frame error rate
+    undetected: int = 0                 # converged to a wrong codeword
+    iter_percentiles: tuple = ()        # iterations at p50 / p90 / p99 / max
 
     def row(self) -> Dict:
         return dataclasses.asdict(self)
+
+
+def wilson(k: int, n: int, z: float = 1.96):
+    """Wilson score interval for k errors in n frames."""
+    if n == 0:
+        return (0.0, 1.0)
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / d
+    return (max(0.0, c - h), min(1.0, c + h))
+
+
+def _stats(torch, code, out, frames: int):
+    """BER, FER, its interval, undetected errors and iteration percentiles."""
+    errs = _errors(torch, out.bits, code.n)
+    fe = int((errs > 0).sum().item())
+    und = int(((errs > 0) & (out.converged == 1)).sum().item())
+    it = out.iters.double()
+    q = torch.quantile(it[: min(frames, 1 << 24)], torch.tensor([0.5, 0.9, 0.99], dtype=torch.float64,
+                                                                 device=it.device))
+    return dict(ber=float(errs.sum().item()) / (frames * code.n), fer=fe / frames,
+                fer_ci95=wilson(fe, frames), undetected=und,
+                avg_iterations=float(it.mean().item()),
+                unconverged=int((out.converged == 0).sum().item()),
+                iter_percentiles=tuple([float(v) for v in q.tolist()] + [float(it.max().item())]))
 
 
 def _errors(torch, bits, n):
@@ -113,13 +142,9 @@ def run_point(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    errs = _errors(torch, out.bits, code.n)
     return Point(code=code.name, ebn0=ebn0, params=params, frames=frames, y_format=y_format,
-                 ber=float(errs.sum().item()) / (frames * code.n),
-                 fer=float((errs > 0).double().mean().item()),
-                 avg_iterations=float(out.iters.double().mean().item()),
-                 unconverged=int((out.converged == 0).sum().item()), kernel_ms=ms,
-                 info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed)
+                 kernel_ms=ms, info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed,
+                 **_stats(torch, code, out, frames))
 
 
 def run_grid(code, dev_code, ebn0: float, param_list: Sequence[Dict], frames: int, seed: int,
@@ -140,13 +165,10 @@ def run_grid(code, dev_code, ebn0: float, param_list: Sequence[Dict], frames: in
     ms = e0.elapsed_time(e1) / max(len(param_list), 1)
     pts = []
     for pr, out in zip(param_list, outs):
-        errs = _errors(torch, out.bits, code.n)
         pts.append(Point(code=code.name, ebn0=ebn0, params=dict(pr), frames=frames,
-                         y_format=y_format, ber=float(errs.sum().item()) / (frames * code.n),
-                         fer=float((errs > 0).double().mean().item()),
-                         avg_iterations=float(out.iters.double().mean().item()),
-                         unconverged=int((out.converged == 0).sum().item()), kernel_ms=ms,
-                         info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed))
+                         y_format=y_format, kernel_ms=ms,
+                         info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed,
+                         **_stats(torch, code, out, frames)))
     return pts
 
 

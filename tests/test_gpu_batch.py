@@ -190,3 +190,50 @@ def test_batch_graph_replays(torch_dev):
     del g
     for it in items:
         it["dc"].close()
+
+
+def test_batch_with_full_device_jobs_and_graph(torch_dev):
+    """Jobs of 65536 frames or more run in order on the caller's stream beside
+    the forked small ones; eager and graph-replayed results equal
+    one-at-a-time decodes (and the oracle on samples)."""
+    torch = torch_dev
+    c = codes.named_code("C96")
+    dc = ng.Code.from_ldpc(c)
+    p = oracle.Params(w=0.75, theta=-0.6, lam=1.0, eta=0.9, ymax=2.5, t_max=60)
+    sizes = [70000, 300, 65536, 90]
+    ys, outs, refs = [], [], []
+    for i, F in enumerate(sizes):
+        sig = float(np.float32(channel.sigma_from_ebn0(3.0 + 0.25 * i, c.rate)))
+        y = channel.bpsk_awgn_device(F, c.n, sig, seed=200 + i)
+        ys.append((y, sig))
+        outs.append(ng.alloc_outputs(dc, F, "cuda"))
+        refs.append(ng.decode(dc, y, sig, ng.Params(**p.__dict__), 300 + i, frame_base=7 * i))
+    torch.cuda.synchronize()
+    jobs = [ng.job(dc, y, sig, ng.Params(**p.__dict__), 300 + i, outs[i], frame_base=7 * i)
+            for i, (y, sig) in enumerate(ys)]
+    say("batch with full-device jobs")
+    ng.ngdbf_decode_batch(jobs, None)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        assert (o.bits == r.bits).all().item() and (o.iters == r.iters).all().item()
+    y0, sig0 = ys[0]
+    rs = oracle.decode(c, y0[:64].cpu().numpy(), sig0, p, 300, frame_base=0, threads=4)
+    same(host(ng.Outputs(outs[0].bits[:64], outs[0].iters[:64], outs[0].converged[:64])), rs)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ng.ngdbf_decode_batch(jobs, s)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for o in outs:
+            o.iters.fill_(-1)
+        torch.cuda.synchronize()
+        say("replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert (o.bits == r.bits).all().item() and (o.iters == r.iters).all().item()
+    del g
+    dc.close()

@@ -14,3 +14,10 @@ def test_heuristic_lambda_schedule():
     assert [sweep.heuristic_params(e)["lam"] for e in (2.0, 3.0, 3.5, 4.0, 4.5, 5.0)] == \
         [0.99, 0.99, 0.97, 0.94, 0.90, 0.90]
     assert sweep.heuristic_params(3.0)["smooth_window"] == 64
+
+
+def test_wilson_interval():
+    lo, hi = sweep.wilson(0, 100)
+    assert lo == 0.0 and 0.03 < hi < 0.04       # rule of three, roughly
+    lo, hi = sweep.wilson(50, 100)
+    assert abs((lo + hi) / 2 - 0.5) < 1e-12 and 0.40 < lo < 0.41
