@@ -332,14 +332,15 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
             uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
             const Shape *force, Prepared *out, const ngdbf_segment *segments = nullptr,
             int32_t n_segments = 0, int64_t pool_frames = -1) {
+  // host-side validation, parameters first (no device state is touched)
   int rc = check_params(p);
   if (rc) return rc;
-  if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   if (n_frames < 0) return fail(NGDBF_EINVAL, "n_frames < 0");
-  if (n_frames > 0 && (!y || !out_bits || !out_iters))
-    return fail(NGDBF_EINVAL, "y, out_bits and out_iters are required");
   if (!sigma && (!(sigma_scalar >= 0.0f) || !std::isfinite(sigma_scalar)))
     return fail(NGDBF_EINVAL, "sigma_scalar must be finite and >= 0");
+  if (!code) return fail(NGDBF_EINVAL, "code is NULL");
+  if (n_frames > 0 && (!y || !out_bits || !out_iters))
+    return fail(NGDBF_EINVAL, "y, out_bits and out_iters are required");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NGDBF_EDEVICE, "no HIP device");
   if (dev != code->device)

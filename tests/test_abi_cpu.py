@@ -125,3 +125,32 @@ def test_params_validation_of_the_extended_decoders(L):
 def test_objective_rejects_bad_arguments(L):
     with pytest.raises(ng.NgdbfError, match="code is NULL"):
         ng.ngdbf_objective(None, None, 0, 1, 2.5, None, None, 0)
+
+
+@pytest.mark.parametrize("sigma", [-0.5, float("nan"), float("inf")])
+def test_decode_rejects_bad_sigma(L, sigma):
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    with pytest.raises(ng.NgdbfError, match="sigma_scalar"):
+        ng.ngdbf_decode(None, None, 4, None, sigma, p, 1, 0, None, None, None, 0)
+
+
+def test_decode_rejects_negative_frames_and_bad_params(L):
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    with pytest.raises(ng.NgdbfError, match="n_frames < 0"):
+        ng.ngdbf_decode(None, None, -1, None, 0.5, p, 1, 0, None, None, None, 0)
+    for bad, msg in ((dict(t_max=-1), "t_max"), (dict(lam=0.0), "lambda"), (dict(lam=1.5), "lambda"),
+                     (dict(w=0.0), "w must"), (dict(eta=-1.0), "eta"),
+                     (dict(theta=float("nan")), "theta"), (dict(smooth_window=-2), "smooth_window")):
+        q = ng.Params(**{**ng.Params().__dict__, **bad}).c(ng.NGDBF_Y_F32)
+        with pytest.raises(ng.NgdbfError, match=msg):
+            ng.ngdbf_decode(None, None, 4, None, 0.5, q, 1, 0, None, None, None, 0)
+    q = ng.Params().c(7)
+    with pytest.raises(ng.NgdbfError, match="unknown y_format"):
+        ng.ngdbf_decode(None, None, 4, None, 0.5, q, 1, 0, None, None, None, 0)
+
+
+def test_create_code_rejects_more_shapes(L):
+    with pytest.raises(ng.NgdbfError, match="row_ptr\\[0\\]"):
+        ng.ngdbf_create_code(4, 2, [1, 2, 4], [0, 1, 2, 3])
+    with pytest.raises(ng.NgdbfError, match="need 1 <= m < n"):
+        ng.ngdbf_create_code(70000, 2, [0, 1, 2], [0, 1])
