@@ -147,6 +147,64 @@ def run_point(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
                  **_stats(torch, code, out, frames))
 
 
+def run_point_chunked(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
+                      chunk: int, state_path: str, y_format: str = "f32",
+                      max_chunks: Optional[int] = None) -> Optional[Dict]:
+    """A Monte Carlo point in chunks of `chunk` frames with a JSON checkpoint
+    after each chunk.  Chunk c decodes frames c*chunk ... with frame_base =
+    c*chunk (the noise key) and samples drawn from seed (seed, c), so a run
+    resumed from its checkpoint gives bit-identical totals.  Returns the
+    totals when every chunk is done, else None (stopped after max_chunks)."""
+    import numpy as np
+    import torch
+
+    from synth import channel
+
+    n_chunks = (frames + chunk - 1) // chunk
+    key = {"code": code.name, "code_digest": code.digest(), "ebn0": ebn0, "params": params,
+           "frames": frames, "chunk": chunk, "seed": seed, "y_format": y_format}
+    state = {"key": key, "next_chunk": 0, "bit_errors": 0, "frame_errors": 0, "undetected": 0,
+             "unconverged": 0, "iterations": 0, "iteration_histogram": [0] * (params["t_max"] + 1)}
+    if os.path.exists(state_path):
+        with open(state_path) as f:
+            old = json.load(f)
+        if old.get("key") != key:
+            raise ValueError(f"{state_path} holds a different run")
+        state = old
+    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
+    p = ng.Params(**params)
+    done = 0
+    while state["next_chunk"] < n_chunks:
+        if max_chunks is not None and done >= max_chunks:
+            return None
+        c = state["next_chunk"]
+        fc = min(chunk, frames - c * chunk)
+        y = channel.bpsk_awgn_device(fc, code.n, sigma, seed=seed * 1000003 + c)
+        if y_format == "i8":
+            y = channel.quantize_int8(y)
+        out = ng.decode(dev_code, y, sigma, p, seed, frame_base=c * chunk)
+        errs = _errors(torch, out.bits, code.n)
+        hist = torch.bincount(out.iters.long(), minlength=params["t_max"] + 1)
+        state["bit_errors"] += int(errs.sum().item())
+        state["frame_errors"] += int((errs > 0).sum().item())
+        state["undetected"] += int(((errs > 0) & (out.converged == 1)).sum().item())
+        state["unconverged"] += int((out.converged == 0).sum().item())
+        state["iterations"] += int(out.iters.long().sum().item())
+        state["iteration_histogram"] = [a + int(b) for a, b in
+                                        zip(state["iteration_histogram"], hist.tolist())]
+        state["next_chunk"] = c + 1
+        tmp = state_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(state, f)
+        os.replace(tmp, state_path)
+        done += 1
+    fe = state["frame_errors"]
+    return {**key, "ber": state["bit_errors"] / (frames * code.n), "fer": fe / frames,
+            "fer_ci95": wilson(fe, frames), "undetected": state["undetected"],
+            "unconverged": state["unconverged"], "avg_iterations": state["iterations"] / frames,
+            "iteration_histogram": state["iteration_histogram"]}
+
+
 def run_grid(code, dev_code, ebn0: float, param_list: Sequence[Dict], frames: int, seed: int,
              y_format: str = "f32") -> List[Point]:
     """Many parameter sets on the same received frames, as one batched launch
@@ -254,6 +312,9 @@ def main(argv: Optional[Sequence[str]] = None) -> int:
     ap.add_argument("--vary", default="", help="name=lo:hi:step (vary mode)")
     ap.add_argument("--seed", type=int, default=0, help="0: 2000 + 10 * Eb/N0")
     ap.add_argument("--out", default="", help="append JSON lines here (default stdout)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="ebn0 mode: frames per chunk, checkpointed to --state (resumable)")
+    ap.add_argument("--state", default="", help="checkpoint file prefix for --chunk")
     args = ap.parse_args(argv)
 
     import torch
@@ -281,7 +342,11 @@ def main(argv: Optional[Sequence[str]] = None) -> int:
     t0 = time.time()
     for e in _range(args.ebn0):
         seed = args.seed or int(2000 + round(10 * e))
-        if args.mode == "ebn0":
+        if args.mode == "ebn0" and args.chunk:
+            path = f"{args.state or 'sweep_state'}_{code.name}_{e}.json"
+            emit(run_point_chunked(code, dc, e, params_at(e), args.frames, seed, args.chunk, path,
+                                   args.y_format))
+        elif args.mode == "ebn0":
             emit(run_point(code, dc, e, params_at(e), args.frames, seed, args.y_format).row())
         elif args.mode == "vary":
             name, spec = args.vary.split("=")

@@ -47,3 +47,16 @@ def test_successive_approximation(c96):
     b = sweep.run_point(c, dc, 3.0, best, 4096, seed=6)
     s = sweep.run_point(c, dc, 3.0, start, 4096, seed=6)
     assert (b.ber, b.avg_iterations) <= (s.ber, s.avg_iterations)
+
+
+def test_chunked_point_resumes_bit_identically(c96, tmp_path):
+    """A Monte Carlo point stopped after two chunks and resumed from its
+    checkpoint gives the same totals as an uninterrupted run."""
+    c, dc = c96
+    pr = {**sweep.heuristic_params(3.0), "t_max": 80}
+    a = sweep.run_point_chunked(c, dc, 3.0, pr, 5000, 9, 1024, str(tmp_path / "a.json"))
+    assert sweep.run_point_chunked(c, dc, 3.0, pr, 5000, 9, 1024, str(tmp_path / "b.json"),
+                                   max_chunks=2) is None
+    b = sweep.run_point_chunked(c, dc, 3.0, pr, 5000, 9, 1024, str(tmp_path / "b.json"))
+    assert a == b
+    assert sum(a["iteration_histogram"]) == 5000
