@@ -187,7 +187,14 @@ struct Layout {
   bool ext = false;     // extended decoder: two 64-bit reduction words
   int stream_len = 0;   // noise-reuse samples per frame
   bool lists = true;    // per-wave Box-Muller lists (the settle-test path)
+  bool packed = false;  // quantized multi-bit decoder with noise reuse in 16-bit lanes
+  int t_max = 0;
 };
+
+// samples per shifted copy of the packed decoder's reversed stream
+int packed_stream_lr(const Layout &L) { return L.stream_len > 0 ? (L.stream_len + 3 + 3) & ~3 : 0; }
+// words of the packed decoder's threshold table theta~(u), u = 0..T (int16)
+int packed_table_words(const Layout &L) { return L.packed ? ((L.t_max + 2) / 2 + 1) & ~1 : 0; }
 
 int list_words(const Layout &L) { return L.lists ? ngdbf::kEntryWords * ngdbf::kListCap : 0; }
 
@@ -207,7 +214,10 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
     w += 4;
     p.stream_off = w;
     p.clear_words = w;
-    w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
+    if (L.packed)
+      w += 2 * packed_stream_lr(L);       // four shifted int16 copies
+    else
+      w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
   } else {
     p.clear_words = w;
   }
@@ -215,15 +225,27 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
   return p;
 }
 
-int slots_offset(const ngdbf_code *c) { return (c->table_words + 1) & ~1; }
+// LDS words: code tables | [threshold table] | frame slots | wave lists
+int qtab_offset(const ngdbf_code *c) { return (c->table_words + 1) & ~1; }
+int slots_offset(const ngdbf_code *c, const Layout &L) {
+  return qtab_offset(c) + packed_table_words(L);
+}
 
 size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
-  return ((size_t)slots_offset(c) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
+  return ((size_t)slots_offset(c, L) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
           (size_t)(sh.block() / 64) * list_words(L)) * 4;
 }
 
 bool extended(const ngdbf_params *p) {
   return p->variant != NGDBF_MULTI || p->quant_bits != 0 || p->noise_reuse != 0;
+}
+
+// The quantized multi-bit decoder with noise reuse runs in packed 16-bit lanes
+// (its threshold table of T + 1 entries lives in LDS, so T is bounded).
+constexpr int kPackedMaxT = 4095;
+bool packed_decoder(const ngdbf_params *p) {
+  return p->variant == NGDBF_MULTI && p->quant_bits != 0 && p->noise_reuse != 0 &&
+         p->t_max <= kPackedMaxT;
 }
 
 Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
@@ -233,6 +255,8 @@ Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
   L.stream_len = (p->noise_reuse && p->t_max > 0) ? c->n + p->t_max - 1 : 0;
   // the lists serve multi-bit rounds with per-bit draws only
   L.lists = !(p->noise_reuse || p->variant == NGDBF_SINGLE);
+  L.packed = packed_decoder(p);
+  L.t_max = p->t_max;
   return L;
 }
 
@@ -264,8 +288,9 @@ int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
   }
   const int nq = (c->n + 3) / 4;
   // the extended decoders keep more per-bit state: at most two quads per
-  // lane (more waves per frame) keeps them out of register spills
-  const bool few_quads = L.ext;
+  // lane (more waves per frame) keeps them out of register spills (the packed
+  // quantized decoder holds two bits per register and needs no such limit)
+  const bool few_quads = L.ext && !L.packed;
   for (const auto &sh : kShapes) {
     if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
     if (nq <= 64 * sh[0] * sh[1]) {
@@ -325,6 +350,7 @@ struct Prepared {
   int dev;
   int y_format;
   bool ext;
+  bool packed;
 };
 
 int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
@@ -391,8 +417,11 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.uw_words = (n + 3) / 4;
   a.xw_words = (n + 31) / 32;
   const SlotPlan plan = slot_plan(code, L);
+  a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
   a.slot_words = plan.slot_words;
-  a.slots_off = slots_offset(code);
+  a.slots_off = slots_offset(code, L);
+  a.qtab_off = qtab_offset(code);
+  a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;
   a.clear_words = plan.clear_words;
@@ -411,12 +440,12 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   } else {
     a.qc = a.qtop = a.wq = a.qbound = 0.0f;
   }
-  a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
   out->sh = sh;
   out->lds = lds_bytes(code, sh, L);
   out->dev = dev;
   out->y_format = p->y_format;
   out->ext = L.ext;
+  out->packed = L.packed;
   return ok();
 }
 
@@ -429,6 +458,8 @@ int enqueue(const Prepared &pr, hipStream_t s) {
       return ngdbf_host::dispatch_ext_single(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
     if (pr.a.variant == NGDBF_MODE_SWITCH)
       return ngdbf_host::dispatch_ext_switch(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
+    if (pr.packed)
+      return ngdbf_host::dispatch_ext_packed(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
     return ngdbf_host::dispatch_ext_multi(pr.sh, pr.a, pr.lds, pr.dev, s, pr.y_format, trace);
   }
   constexpr int kBase = ngdbf::kExtNone;

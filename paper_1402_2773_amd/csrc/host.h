@@ -61,12 +61,15 @@ int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, h
 }
 
 // The extended decoders, one translation unit per family
-// (decode_ext_multi.hip, decode_ext_single.hip, decode_ext_switch.hip).
+// (decode_ext_multi.hip, decode_ext_single.hip, decode_ext_switch.hip,
+// decode_ext_packed.hip).
 int dispatch_ext_multi(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
                        hipStream_t s, int y_format, bool trace);
 int dispatch_ext_single(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
                         hipStream_t s, int y_format, bool trace);
 int dispatch_ext_switch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
+                        hipStream_t s, int y_format, bool trace);
+int dispatch_ext_packed(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
                         hipStream_t s, int y_format, bool trace);
 
 // Instances of one family for every y format and trace setting.

@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "../../include/ngdbf.h"
 #include "noise.h"
@@ -46,6 +47,18 @@ constexpr int kExtNone = 0;    // multi-bit, binary32, per-bit draws
 constexpr int kExtMulti = 1;   // multi-bit with quantization and/or noise reuse
 constexpr int kExtSingle = 2;  // single-bit flips (Step 3a)
 constexpr int kExtSwitch = 3;  // mode switching (Step 3b, then 3a)
+constexpr int kExtQuantReuse = 4;  // multi-bit, quantized, noise reuse: packed 16-bit lanes
+
+// packed pairs of signed 16-bit integers (two bits of a quad per register)
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ short2_t as_s2(uint32_t v) { return __builtin_bit_cast(short2_t, v); }
+__device__ __forceinline__ uint32_t as_u32(short2_t v) { return __builtin_bit_cast(uint32_t, v); }
+
+// x_k g(y_k) of a bit that can never flip (past the code, or a NaN sample):
+// with |g(w) S_k| <= 255 * 15 and |g(q_k)|, |theta~| <= 255, E~_k stays far
+// above every threshold and within int16
+constexpr int kNeverFlip = 16383;
 
 struct DecodeArgs {
   // code tables, uint16, staged into LDS: col_idx (N(i), CSR) | row_idx
@@ -92,6 +105,8 @@ struct DecodeArgs {
   int32_t stream_q;     // ceil(stream_len / 4): sample i sits at (i & 3) * stream_q + (i >> 2)
   int32_t list_words;   // Box-Muller list words per wave (0 when no list is used)
   int32_t clear_words;  // slot words cleared per frame (the stream is rewritten)
+  int32_t qtab_off;     // kExtQuantReuse: LDS word offset of theta~(u), u = 0..T (int16)
+  int32_t stream_lr;    // kExtQuantReuse: int16 samples per shifted copy of the stream
 };
 
 template <int YFMT>
@@ -298,7 +313,24 @@ decode_kernel(DecodeArgs a) {
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
   uint32_t *list = lds + a.slots_off + a.frames_per_block * a.slot_words + wave * a.list_words;
-  const bool quant = (EXT == kExtMulti || EXT == kExtSingle) && a.quant_bits > 0;
+  const bool quant =
+      (EXT == kExtMulti || EXT == kExtSingle || EXT == kExtQuantReuse) && a.quant_bits > 0;
+  constexpr bool QR = EXT == kExtQuantReuse;
+  // kExtQuantReuse: the quantized thresholds theta~(u) = g(theta lambda^u)
+  // (Sec. V-A) for every non-flip count u <= T, theta lambda^u by repeated
+  // binary32 multiplication, once per workgroup
+  int16_t *qtab = (int16_t *)(lds + a.qtab_off);
+  if (QR && tid == 0) {
+    float th = a.theta;
+    for (int u = 0; u <= a.t_max; ++u) {
+      if (u) th = th * a.lambda;
+      qtab[u] = (int16_t)quant_half(th, a.qc, a.qtop);
+    }
+  }
+  // kExtQuantReuse: the stream reversed, R[i] = g(q) of element L - 1 - i, in
+  // four copies shifted by 0..3 samples, so that a lane reads its quad's four
+  // samples as one aligned 8-byte word in every round
+  int16_t *qstream = (int16_t *)(slot + a.stream_off);
   __syncthreads();
 
   const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
@@ -332,7 +364,35 @@ decode_kernel(DecodeArgs a) {
       // the argmin word starts at "no candidate"
       for (int i = ft; i < a.clear_words; i += FT)
         slot[i] = (i == a.red_off || i == a.red_off + 1) ? 0xFFFFFFFFu : 0u;
-      if (a.noise_reuse) {
+      if (QR) {
+        // sample idx goes to R[L - 1 - idx] of each copy; R[L .. L + 2] = 0
+        const int L = a.stream_len;
+        const int nsq = (L + 3) >> 2;
+        for (int jq = ft; jq < nsq; jq += FT) {
+          const Words4 wd = philox4x32_10((uint32_t)jq, 0xFFFFFFFFu, (uint32_t)frame,
+                                          (uint32_t)(frame >> 32), key0, key1);
+          float z[4];
+          bm_pair(wd.w0, wd.w1, z[0], z[1]);
+          bm_pair(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int idx = 4 * jq + b;
+            if (idx < L) {
+              const int i = L - 1 - idx;
+              const int16_t v = (int16_t)quant_half(qs * z[b], a.qc, a.qtop);
+#pragma unroll
+              for (int ph = 0; ph < 4; ++ph)
+                if (i >= ph) qstream[ph * a.stream_lr + (i - ph)] = v;
+            }
+          }
+        }
+        if (ft < 3 && L > 0) {
+          const int i = L + ft;
+#pragma unroll
+          for (int ph = 0; ph < 4; ++ph)
+            if (i >= ph) qstream[ph * a.stream_lr + (i - ph)] = 0;
+        }
+      } else if (a.noise_reuse) {
         // the shift-register chain (Sec. V-B): sample j of the frame's stream
         // is draw j & 3 of quad j >> 2 under the iteration word 0xFFFFFFFF
         const int nsq = (a.stream_len + 3) >> 2;
@@ -362,6 +422,9 @@ decode_kernel(DecodeArgs a) {
     uint32_t deg4[QPL];    // column degrees, one nibble per bit (irregular codes)
     uint32_t xneg = 0;     // bit 4r+b: x_k = -1 for k = 4 j_r + b
     uint32_t vmask = 0;    // bit 4r+b: k = 4 j_r + b is a bit of the code
+    // kExtQuantReuse state, one register per pair of bits (4r+2p, 4r+2p+1):
+    // x_k g(y_k), the non-flip count u_k and (irregular codes) the degree
+    uint32_t xy2[QPL * 2], u2[QPL * 2], dg2[QPL * 2];
 #pragma unroll
     for (int r = 0; r < QPL; ++r) {
       const int j = ft + FT * r;
@@ -381,6 +444,20 @@ decode_kernel(DecodeArgs a) {
         thr[4 * r + b] = (j < nq && k < n) ? a.theta : -INFINITY;
         vmask |= (j < nq && k < n ? 1u : 0u) << (4 * r + b);
         nib |= (v < 0.0f ? 1u : 0u) << b;
+        if (QR) {
+          // x(0) g(y) = |g(y)|; bits past n and NaN samples never flip
+          const float gy = yv[4 * r + b];
+          const int xyk = (j < nq && k < n && gy == gy) ? (int)fabsf(gy) : kNeverFlip;
+          const int dk = REG ? a.dv : (int)((dg >> (4 * b)) & 15u);
+          const int sh = 16 * (b & 1);
+          if ((b & 1) == 0) {
+            xy2[2 * r + (b >> 1)] = 0u;
+            u2[2 * r + (b >> 1)] = 0u;
+            dg2[2 * r + (b >> 1)] = 0u;
+          }
+          xy2[2 * r + (b >> 1)] |= ((uint32_t)xyk & 0xFFFFu) << sh;
+          dg2[2 * r + (b >> 1)] |= ((uint32_t)dk & 0xFFFFu) << sh;
+        }
       }
       X2[2 * r] = X2[2 * r + 1] = (kXBias << 16) | kXBias;
       deg4[r] = dg;
@@ -451,49 +528,102 @@ decode_kernel(DecodeArgs a) {
       // ---- decisions for every owned bit (Steps 2, 3)
       uint32_t flip = 0;     // bit 4r+b: flip in this round
       const bool single = EXT == kExtSingle || (EXT == kExtSwitch && !mu);
-      if (X && (single || a.noise_reuse)) {
-        // every bit's E_k with its draw: from the chain (Sec. V-B) or from
-        // its own Philox quad
-        uint64_t best = ~0ull;
+      if (QR) {
+        // E~_k = x_k g(y_k) + g(w) S_k + g(q_k) < theta~(u_k), two bits per
+        // register in signed 16-bit lanes (exact: every term is a small integer)
+        const short2_t w2 = {(short)a.wq, (short)a.wq};
+        const int sbase = a.stream_len - n - t;  // R index of bit 4j's sample is sbase + 4j
 #pragma unroll
         for (int r = 0; r < QPL; ++r) {
           const int j = ft + FT * r;
           const int jc = j < nq ? j : nq - 1;
-          float z4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (!a.noise_reuse) {
-            const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
-                                            (uint32_t)(frame >> 32), key0, key1);
-            bm_pair(wd.w0, wd.w1, z4[0], z4[1]);
-            bm_pair(wd.w2, wd.w3, z4[2], z4[3]);
-          }
           const uint32_t u4 = uw[jc];
+          const int sidx = sbase + 4 * jc;
+          const int ph = sidx & 3;
+          const uint2 sv = *(const uint2 *)(qstream + ph * a.stream_lr + (sidx - ph));
+          uint32_t fq = 0;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int q = 4 * r + b;
-            const int k = 4 * j + b;
-            const bool valid = (vmask >> q) & 1u;
-            const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
-            const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
-            const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
-            const float av = __builtin_fmaf(weff, Sf, xy);
-            float E;
-            if (a.noise_reuse) {
-              // bit k holds element n - 1 + t - k of the stream in round t
-              const int idx = n - 1 + t - k;
-              const float v = valid ? stream[(idx & 3) * a.stream_q + (idx >> 2)] : 0.0f;
-              E = quant ? av + v : __builtin_fmaf(qs, v, av);
-            } else {
-              E = quant ? av + quant_half(qs * z4[b], a.qc, a.qtop) : __builtin_fmaf(qs, z4[b], av);
+          for (int pp = 0; pp < 2; ++pp) {
+            const int i2 = 2 * r + pp;
+            // unsatisfied-check counts of the pair, one per 16-bit lane
+            const uint32_t up = ((u4 >> (16 * pp)) & 0xFFu) | (((u4 >> (16 * pp + 8)) & 0xFFu) << 16);
+            const short2_t dgv = REG ? short2_t{(short)a.dv, (short)a.dv} : as_s2(dg2[i2]);
+            const short2_t S2 = dgv - (as_s2(up) << (short)1);
+            const short2_t E2 = as_s2(xy2[i2]) + w2 * S2 + as_s2(pp ? sv.y : sv.x);
+            const uint32_t uu = u2[i2];
+            const short2_t th2 = {qtab[uu & 0xFFFFu], qtab[uu >> 16]};
+            // sign of E - theta: 1 where the bit flips
+            const uint32_t f2 = (as_u32(E2 - th2) >> 15) & 0x00010001u;
+            fq |= ((f2 & 1u) | ((f2 >> 15) & 2u)) << (2 * pp);
+            // non-flips count up (Sec. V-A); flips negate x_k g(y_k)
+            u2[i2] = uu + (f2 ^ 0x00010001u);
+            const uint32_t m = f2 * 0xFFFFu;
+            xy2[i2] = as_u32(as_s2(xy2[i2] ^ m) - as_s2(m));
+          }
+          flip |= fq << (4 * r);
+        }
+      } else if (X && (single || a.noise_reuse)) {
+        // every bit's E_k with its draw: from the chain (Sec. V-B) or from
+        // its own Philox quad.  The draw source, the arithmetic and the rule
+        // are compile-time inside `direct`, so its unrolled loop carries no
+        // uniform branches; the selection below happens once per round.
+        auto direct = [&](auto reuse_c, auto quant_c, auto single_c) -> uint64_t {
+          constexpr bool kReuse = decltype(reuse_c)::value;
+          constexpr bool kQuant = decltype(quant_c)::value;
+          constexpr bool kSingle = decltype(single_c)::value;
+          uint64_t best = ~0ull;
+#pragma unroll
+          for (int r = 0; r < QPL; ++r) {
+            const int j = ft + FT * r;
+            const int jc = j < nq ? j : nq - 1;
+            float z4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (!kReuse) {
+              const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
+                                              (uint32_t)(frame >> 32), key0, key1);
+              bm_pair(wd.w0, wd.w1, z4[0], z4[1]);
+              bm_pair(wd.w2, wd.w3, z4[2], z4[3]);
             }
-            if (single) {
-              // Step 3a: the least E_k, ties to the lowest k, NaN never chosen
-              const uint64_t key = argmin_key(E, k);
-              if (valid && E == E && key < best) best = key;
-            } else {
-              const float th = (quant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
-              flip |= (E < th ? 1u : 0u) << q;
+            const uint32_t u4 = uw[jc];
+            // bit 4j + b holds element n - 1 + t - 4j - b of the stream in
+            // round t; the four rows interleave it (sample i at row i & 3)
+            const int c0 = n - 1 + t - 4 * j;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const int q = 4 * r + b;
+              const int k = 4 * j + b;
+              const bool valid = (vmask >> q) & 1u;
+              const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
+              const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
+              const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
+              const float av = __builtin_fmaf(weff, Sf, xy);
+              float E;
+              if (kReuse) {
+                const int idx = c0 - b;
+                const float v = valid ? stream[(idx & 3) * a.stream_q + (idx >> 2)] : 0.0f;
+                E = kQuant ? av + v : __builtin_fmaf(qs, v, av);
+              } else {
+                E = kQuant ? av + quant_half(qs * z4[b], a.qc, a.qtop) : __builtin_fmaf(qs, z4[b], av);
+              }
+              if (kSingle) {
+                // Step 3a: the least E_k, ties to the lowest k, NaN never chosen
+                const uint64_t key = argmin_key(E, k);
+                if (valid && E == E && key < best) best = key;
+              } else {
+                const float th = (kQuant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
+                flip |= (E < th ? 1u : 0u) << q;
+              }
             }
           }
+          return best;
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        uint64_t best = ~0ull;
+        if (single) {
+          if (a.noise_reuse) best = quant ? direct(T_{}, T_{}, T_{}) : direct(T_{}, F_{}, T_{});
+          else best = quant ? direct(F_{}, T_{}, T_{}) : direct(F_{}, F_{}, T_{});
+        } else {
+          (void)(quant ? direct(T_{}, T_{}, F_{}) : direct(T_{}, F_{}, F_{}));
         }
         if (single) {
           best = wave_min_u64(best);
@@ -578,7 +708,7 @@ decode_kernel(DecodeArgs a) {
       }
 
       // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
-      if (a.lambda != 1.0f && !single) {
+      if (!QR && a.lambda != 1.0f && !single) {
 #pragma unroll
         for (int q = 0; q < QPL * 4; ++q)
           if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;

@@ -99,9 +99,12 @@ def test_shape_validation(torch_dev):
     assert ng.ngdbf_code_get_shape(dc.handle) == (4, 1, 1)
     ng.ngdbf_code_set_shape(dc.handle, 0, 0, 0)
     assert ng.ngdbf_code_get_shape(dc.handle) == (1, 4, 16)
-    # the extended decoders default to at most two quads per lane
-    pq = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75).c(ng.NGDBF_Y_F32)
-    assert ng.ngdbf_code_get_shape(dc.handle, pq) == (2, 2, 1)
+    # the extended decoders default to at most two quads per lane, except the
+    # packed quantized one (whose stream leaves LDS for 8 frames per workgroup)
+    ps = ng.Params(variant=ng.NGDBF_SINGLE).c(ng.NGDBF_Y_F32)
+    assert ng.ngdbf_code_get_shape(dc.handle, ps) == (2, 2, 1)
+    pq = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75, t_max=300).c(ng.NGDBF_Y_F32)
+    assert ng.ngdbf_code_get_shape(dc.handle, pq) == (1, 4, 8)
     dc.close()
 
 

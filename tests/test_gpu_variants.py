@@ -174,11 +174,12 @@ def test_variant_golden_examples(torch_dev):
 
 
 def test_reuse_long_T_and_T0(torch_dev):
-    """Noise reuse with T = 0 (no stream) and with a long T (large stream)."""
+    """Noise reuse with T = 0 (no stream), with a long T (large stream) and
+    with T beyond the packed decoder's threshold table (general path)."""
     c = codes.named_code("C96")
     sig = np.float32(channel.sigma_from_ebn0(2.0, c.rate))
     y = channel.bpsk_awgn(200, c.n, sig, seed=111)
-    for T in (0, 1, 1500):
+    for T in (0, 1, 1500, 5000):
         p = oracle.Params(**{**CASES["quant4_reuse"].__dict__, "t_max": T, "smooth_window": 0})
         say("reuse T", T)
         g, r = run_both(torch_dev, "C96", y, sig, p, seed=112, trace=T <= 100)
