@@ -198,15 +198,16 @@ int packed_table_words(const Layout &L) { return L.packed ? ((L.t_max + 2) / 2 +
 
 int list_words(const Layout &L) { return L.lists ? ngdbf::kEntryWords * ngdbf::kListCap : 0; }
 
-// Word offsets within one frame slot: s | u | x | flips | count | events
+// Word offsets within one frame slot: s | u | x | flips | count | 2 event
+// counters | toggles | events
 // [| reductions | stream]; even, so that 64-bit LDS atomics are aligned.
 struct SlotPlan {
   int red_off = 0, stream_off = 0, clear_words = 0, slot_words = 0;
 };
 
 SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
-  int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 2 +
-          ngdbf::kEventCap;
+  int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 3 +
+          (c->m + 31) / 32 + ngdbf::kEventCap;
   SlotPlan p;
   if (L.ext) {
     w = (w + 1) & ~1;

@@ -307,8 +307,9 @@ decode_kernel(DecodeArgs a) {
   uint32_t *xw = uw + a.uw_words;          // [xw_words] x / output bits
   uint32_t *fw = xw + a.xw_words;          // [xw_words] flip bits (trace)
   uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
-  uint32_t *evn = cnt + 1;                 // events listed this round
-  uint32_t *evl = evn + 1;                 // [kEventCap] toggle events
+  uint32_t *evn = cnt + 1;                 // [2] events listed (rounds alternate)
+  uint32_t *tw = evn + 2;                  // [sw_words] checks toggled this round
+  uint32_t *evl = tw + a.sw_words;         // [kEventCap] toggle events
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
@@ -723,10 +724,11 @@ decode_kernel(DecodeArgs a) {
         }
       }
       frame_sync<WPF>();  // every wave has read u before any toggle lands
-      // each flip toggles s_i of its checks; each toggle is an event (i, +-1)
-      // for the u of the check's bits, applied below by all lanes at once
+      // 1. each flip toggles s_i of its checks: collect the round's toggles in
+      //    a bit row (no atomic result is waited for)
+      uint32_t *evc = evn + (t & 1);
+      if (ft == 0) evn[(t + 1) & 1] = 0u;  // the next round's event counter
       uint32_t fl = flip;
-      int32_t dcnt = 0;
       while (fl) {
         const int q = __builtin_ctz(fl);
         fl &= fl - 1;
@@ -735,30 +737,50 @@ decode_kernel(DecodeArgs a) {
         const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
         for (int e = c0; e < c1; ++e) {
           const int i = tab.row_idx[e];
-          const uint32_t old = atomicXor(&sw[i >> 5], 1u << (i & 31));
-          const bool became_unsat = ((old >> (i & 31)) & 1u) == 0u;
-          dcnt += became_unsat ? 1 : -1;
-          const uint32_t ev = ((uint32_t)i << 1) | (became_unsat ? 0u : 1u);
-          const uint32_t slotn = REG ? atomicAdd(evn, 1u) : (uint32_t)kEventCap;
+          atomicXor(&tw[i >> 5], 1u << (i & 31));
+        }
+      }
+      frame_sync<WPF>();
+      // 2. the owner lane of each syndrome word applies its toggles and lists
+      //    one event (i, +-1) per toggled check, its slots taken with a single
+      //    counter update (owner lanes update the counter at the same time)
+      int32_t dcnt = 0;
+      for (int wd = ft; wd < a.sw_words; wd += FT) {
+        const uint32_t tg = tw[wd];
+        if (!tg) continue;
+        const uint32_t sn = sw[wd] ^ tg;
+        sw[wd] = sn;
+        tw[wd] = 0u;
+        dcnt += 2 * __builtin_popcount(sn & tg) - __builtin_popcount(tg);
+        uint32_t slotn = REG ? atomicAdd(evc, (uint32_t)__builtin_popcount(tg)) : (uint32_t)kEventCap;
+        uint32_t bits = tg;
+        while (bits) {
+          const int bb = __builtin_ctz(bits);
+          bits &= bits - 1;
+          const int i = 32 * wd + bb;
+          const bool unsat_now = ((sn >> bb) & 1u) != 0u;
           if (slotn < (uint32_t)kEventCap) {
-            evl[slotn] = ev;
+            evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
           } else {
             // list full (or an irregular code): apply the event here
-            const uint32_t d = became_unsat ? 1u : 0xFFFFFFFFu;
+            const uint32_t d = unsat_now ? 1u : 0xFFFFFFFFu;
             const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
             for (int e2 = r0; e2 < r1; ++e2) {
               const int k2 = tab.col_idx[e2];
               atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
             }
           }
+          ++slotn;
         }
       }
       if (dcnt) atomicAdd(cnt, (uint32_t)dcnt);
       if (REG) {
+        // 3. every listed event moves u of its check's d_c bits, spread over
+        //    all lanes of the frame
         frame_sync<WPF>();
-        const uint32_t nev = *(volatile uint32_t *)evn;
+        const uint32_t nev = *(volatile uint32_t *)evc;
         const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
-        const uint32_t nup = listed * (uint32_t)a.dc;  // one u update per lane
+        const uint32_t nup = listed * (uint32_t)a.dc;
         for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {
           const uint32_t e = (x * a.dc_recip) >> 20;    // x / d_c, exact here
           const uint32_t ev = evl[e];
@@ -767,8 +789,6 @@ decode_kernel(DecodeArgs a) {
           const int k2 = tab.col_idx[i * a.dc + (int)(x - e * a.dc)];
           atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
         }
-        frame_sync<WPF>();
-        if (ft == 0) *evn = 0u;
       }
       frame_sync<WPF>();
       if (TRACE) {
