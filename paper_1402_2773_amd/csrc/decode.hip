@@ -188,6 +188,8 @@ struct Layout {
   int stream_len = 0;   // noise-reuse samples per frame
   bool lists = true;    // per-wave Box-Muller lists (the settle-test path)
   bool packed = false;  // quantized multi-bit decoder with noise reuse in 16-bit lanes
+  bool lazy = true;     // the base decoder: thresholds from a table and flip counts
+  int thr_words = 0;    // the base decoder's table theta lambda^u, u = 0..T (float)
   int t_max = 0;
 };
 
@@ -196,13 +198,16 @@ int packed_stream_lr(const Layout &L) { return L.stream_len > 0 ? (L.stream_len 
 // words of the packed decoder's threshold table theta~(u), u = 0..T (int16)
 int packed_table_words(const Layout &L) { return L.packed ? ((L.t_max + 2) / 2 + 1) & ~1 : 0; }
 
-int list_words(const Layout &L) { return L.lists ? ngdbf::kEntryWords * ngdbf::kListCap : 0; }
+int list_words(const Layout &L) {
+  if (!L.lists) return 0;
+  return L.lazy ? ngdbf::kEntryWordsLazy * ngdbf::kListCapLazy : ngdbf::kEntryWords * ngdbf::kListCap;
+}
 
 // Word offsets within one frame slot: s | u | x | flips | count | 2 event
-// counters | toggles | events
-// [| reductions | stream]; even, so that 64-bit LDS atomics are aligned.
+// counters | toggles | events [| flip counts] [| reductions | stream]; even,
+// so that 64-bit LDS atomics are aligned.
 struct SlotPlan {
-  int red_off = 0, stream_off = 0, clear_words = 0, slot_words = 0;
+  int red_off = 0, stream_off = 0, clear_words = 0, slot_words = 0, fc_off = 0;
 };
 
 SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
@@ -220,6 +225,10 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
     else
       w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
   } else {
+    if (L.lazy) {
+      p.fc_off = w;
+      w += 2 * ((c->n + 3) / 4);  // two 16-bit counts per word, every pair of every quad
+    }
     p.clear_words = w;
   }
   p.slot_words = (w + 1) & ~1;
@@ -229,7 +238,7 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
 // LDS words: code tables | [threshold table] | frame slots | wave lists
 int qtab_offset(const ngdbf_code *c) { return (c->table_words + 1) & ~1; }
 int slots_offset(const ngdbf_code *c, const Layout &L) {
-  return qtab_offset(c) + packed_table_words(L);
+  return qtab_offset(c) + ((packed_table_words(L) + L.thr_words + 1) & ~1);
 }
 
 size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
@@ -237,8 +246,14 @@ size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
           (size_t)(sh.block() / 64) * list_words(L)) * 4;
 }
 
+// The base decoder keeps its threshold table theta lambda^u (u = 0..T) in
+// LDS; a longer adaptive schedule runs in the extended multi-bit kernel,
+// which keeps one threshold per bit in registers.
+constexpr int kLazyMaxT = 8191;
+
 bool extended(const ngdbf_params *p) {
-  return p->variant != NGDBF_MULTI || p->quant_bits != 0 || p->noise_reuse != 0;
+  return p->variant != NGDBF_MULTI || p->quant_bits != 0 || p->noise_reuse != 0 ||
+         (p->lambda != 1.0f && p->t_max > kLazyMaxT);
 }
 
 // The quantized multi-bit decoder with noise reuse runs in packed 16-bit lanes
@@ -257,6 +272,8 @@ Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
   // the lists serve multi-bit rounds with per-bit draws only
   L.lists = !(p->noise_reuse || p->variant == NGDBF_SINGLE);
   L.packed = packed_decoder(p);
+  L.lazy = !L.ext;
+  L.thr_words = (L.lazy && p->lambda != 1.0f) ? p->t_max + 1 : 0;
   L.t_max = p->t_max;
   return L;
 }
@@ -422,6 +439,8 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.slot_words = plan.slot_words;
   a.slots_off = slots_offset(code, L);
   a.qtab_off = qtab_offset(code);
+  a.thr_off = qtab_offset(code);
+  a.fc_off = plan.fc_off;
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;

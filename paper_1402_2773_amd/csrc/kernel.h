@@ -12,7 +12,9 @@
 //        reuse, the frame's sample stream.  Per wavefront a small Box-Muller
 //        work list.
 //   Registers: each lane owns QPL bit quads (bits 4j .. 4j+3) and keeps their
-//        saturated y_k, thresholds theta_k, smoothing counters and decisions.
+//        saturated y_k, smoothing counters and decisions (the extended
+//        decoders also their thresholds theta_k; the base decoder keeps a
+//        table of theta lambda^u in LDS and per-bit flip counts instead).
 //
 // Frames are independent (Sec. IV): one wavefront decodes a frame of up to
 // 1024 bits with no workgroup barrier in its round loop; longer codes use
@@ -37,6 +39,10 @@ constexpr int kWave = 64;
 constexpr int kListCap = 256;
 // a list entry: the pair's two Philox words, a_k and theta_k of both bits
 constexpr int kEntryWords = 6;
+// the base decoder's list: the pair's two Philox words, a_k of both bits and
+// the pair's index (its thresholds are looked up when the list is finished)
+constexpr int kListCapLazy = 192;
+constexpr int kEntryWordsLazy = 5;
 // check-toggle events per frame and round held for the parallel u update
 constexpr int kEventCap = 256;
 // smoothing counters are 16-bit halves biased by this value
@@ -107,6 +113,11 @@ struct DecodeArgs {
   int32_t clear_words;  // slot words cleared per frame (the stream is rewritten)
   int32_t qtab_off;     // kExtQuantReuse: LDS word offset of theta~(u), u = 0..T (int16)
   int32_t stream_lr;    // kExtQuantReuse: int16 samples per shifted copy of the stream
+  // base decoder (kExtNone): theta lambda^u for u = 0..T (float, LDS word
+  // offset) and the per-frame flip counts (two 16-bit counts per word: bits
+  // 2i and 2i + 1; slot word offset)
+  int32_t thr_off;
+  int32_t fc_off;
 };
 
 template <int YFMT>
@@ -144,6 +155,14 @@ __device__ __forceinline__ void frame_sync() {
   } else {
     __syncthreads();
   }
+}
+
+// The float next above x toward +inf (2^-149 for +-0; +inf and NaN stay).
+// With x = fl(r) the exact r is at most next_up(x).
+__device__ __forceinline__ float next_up(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if (!(fabsf(x) < INFINITY)) return x;
+  return __uint_as_float(x > 0.0f ? u + 1u : (x < 0.0f ? u - 1u : 1u));
 }
 
 // number of set bits of a 64-bit wave mask below this lane
@@ -228,6 +247,39 @@ __device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t to
   wave_sync();  // the list is refilled next
 }
 
+// The same for the base decoder's list: a bit's threshold is theta lambda^u
+// with u = t - (its flips so far) (Sec. III-D), looked up here for the listed
+// bits only.
+__device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32_t total, float qs,
+                                                uint32_t pend, uint64_t posb, uint32_t &flip,
+                                                const float *thtab, const uint32_t *fcw, int t,
+                                                float theta, bool adapt) {
+  wave_sync();
+  for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+    uint32_t *ent = list + kEntryWordsLazy * e;
+    float z0, z1;
+    bm_pair(ent[0], ent[1], z0, z1);
+    const float E0 = __builtin_fmaf(qs, z0, __uint_as_float(ent[2]));
+    const float E1 = __builtin_fmaf(qs, z1, __uint_as_float(ent[3]));
+    float th0 = theta, th1 = theta;
+    if (adapt) {
+      const uint32_t fc = fcw[ent[4]];
+      th0 = thtab[t - (int)(fc & 0xFFFFu)];
+      th1 = thtab[t - (int)(fc >> 16)];
+    }
+    ent[0] = (E0 < th0 ? 1u : 0u) | (E1 < th1 ? 2u : 0u);
+  }
+  wave_sync();
+  while (pend) {
+    const int q2 = __builtin_ctz(pend);
+    pend &= pend - 1;
+    const uint32_t ps = (uint32_t)(posb >> (8 * q2)) & 255u;
+    const uint32_t bits = list[kEntryWordsLazy * ps];
+    flip = (flip & ~(3u << (2 * q2))) | (bits << (2 * q2));
+  }
+  wave_sync();
+}
+
 // Edges of check i (N(i)) and of bit k (M(k)) in the LDS tables.
 struct Tables {
   const uint16_t *col_idx, *row_idx, *row_ptr, *col_ptr;
@@ -262,8 +314,12 @@ struct Tables {
 // by less than 1e-7 relative), and |z| <= radius since |cos|, |sin| <= 1.
 // If a_k - theta_k >= qs * bound, every draw gives E_k >= theta_k (fma
 // rounding is monotone and theta_k is a float): no flip, and the pair needs
-// no transform.  The test runs on squares with a 4e-5 relative slack that
-// covers all rounding.  Every other pair goes through the transform.
+// no transform.  The extended kernels test this on squares with a 4e-5
+// relative slack that covers all rounding.  The base kernel compares a_k with
+// T_c = next_up(fl(theta_t + B_c)) >= theta_t + B_c exactly, where c =
+// clz(a | 1), B_c = next_up(fl(qs s_c)) >= qs s_c and s_c is the bound for c
+// leading zeros with 2e-5 slack; theta_k <= theta_t, so a_k >= T_c implies
+// a_k - theta_k >= qs * bound.  Every other pair goes through the transform.
 //
 // EXT kernels add the other decoders of the paper (EXT = kExtMulti: the
 // multi-bit rule with quantization or noise reuse; kExtSingle: Step 3a;
@@ -310,6 +366,7 @@ decode_kernel(DecodeArgs a) {
   uint32_t *evn = cnt + 1;                 // [2] events listed (rounds alternate)
   uint32_t *tw = evn + 2;                  // [sw_words] checks toggled this round
   uint32_t *evl = tw + a.sw_words;         // [kEventCap] toggle events
+  uint32_t *fcw = slot + a.fc_off;         // LZ: flip counts, two bits per word
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
@@ -317,6 +374,26 @@ decode_kernel(DecodeArgs a) {
   const bool quant =
       (EXT == kExtMulti || EXT == kExtSingle || EXT == kExtQuantReuse) && a.quant_bits > 0;
   constexpr bool QR = EXT == kExtQuantReuse;
+  // The base decoder keeps no per-bit thresholds.  A bit that has flipped F
+  // times in rounds 0 .. t-1 has theta_k = theta lambda^(t - F) (Sec. III-D,
+  // by repeated binary32 multiplication); every bit that never flipped has
+  // theta_t = theta lambda^t, and theta_k <= theta_t for all.  The settle test
+  // uses theta_t (conservative); a listed bit's own theta_k comes from the
+  // table theta lambda^u (u = 0..T, LDS) and the frame's flip counts.
+  constexpr bool LZ = EXT == kExtNone;
+  const bool adapt = a.lambda != 1.0f;
+  float *thtab = (float *)(lds + a.thr_off);
+  if (LZ && adapt && tid == 0) {
+    float th = a.theta;
+    for (int u = 0; u <= a.t_max; ++u) {
+      if (u) th = th * a.lambda;
+      thtab[u] = th;
+    }
+  }
+  // LZ: lane c's radius bound sqrt(2 min(c + 1, 24) ln 2) with a relative
+  // slack of 2e-5, which covers this computation's own rounding (< 3e-7) and
+  // the computed radius's excess over the bound (< 1e-7)
+  const float s_lane = LZ ? sqrtf((float)(lane < 23 ? lane + 1 : 24) * 1.3862944f) * 1.00002f : 0.0f;
   // kExtQuantReuse: the quantized thresholds theta~(u) = g(theta lambda^u)
   // (Sec. V-A) for every non-flip count u <= T, theta lambda^u by repeated
   // binary32 multiplication, once per workgroup
@@ -360,6 +437,9 @@ decode_kernel(DecodeArgs a) {
     // floored at 2^-100 so that the settle test below stays strict: a margin
     // whose square underflows is never taken as settled
     const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
+    // LZ: B_c >= qs s_c exactly, and theta_t of round 0
+    const float bcl = LZ ? next_up(qs * s_lane) : 0.0f;
+    float tht = a.theta;
 
     if (X) {
       // the argmin word starts at "no candidate"
@@ -439,7 +519,10 @@ decode_kernel(DecodeArgs a) {
           if (!REG) dg |= (uint32_t)(tab.col_ptr[k + 1] - tab.col_ptr[k]) << (4 * b);
         }
         // quantized decoder: y~_k = g(y_k) in half steps (Sec. IV-E)
-        yv[4 * r + b] = quant ? quant_half(v, a.qc, a.qtop) : v;
+        // (LZ: a bit past n gets y = +inf: its margin is +inf, it is settled
+        // every round and never flips)
+        yv[4 * r + b] = quant ? quant_half(v, a.qc, a.qtop)
+                              : ((LZ && !(j < nq && k < n)) ? INFINITY : v);
         // a bit past n gets theta = -inf: its margin is +inf, so it is settled
         // every round, never flips and never reaches the output
         thr[4 * r + b] = (j < nq && k < n) ? a.theta : -INFINITY;
@@ -494,7 +577,7 @@ decode_kernel(DecodeArgs a) {
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
     for (;; ++t) {
-      const uint32_t unsat = *(volatile uint32_t *)cnt;
+      const uint32_t unsat = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       // smoothing window t = T-W .. T (Sec. III-E)
       if (W > 0 && t >= T - W) {
 #pragma unroll
@@ -640,21 +723,36 @@ decode_kernel(DecodeArgs a) {
           }
         }
       } else {
+        // LZ: the list holds five words per pair and is finished with the
+        // thresholds looked up; otherwise six words with theta_k in them
+        constexpr uint32_t kCap = LZ ? (uint32_t)kListCapLazy : (uint32_t)kListCap;
+        constexpr int kEW = LZ ? kEntryWordsLazy : kEntryWords;
+        auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
+          if (LZ)
+            flush_list_lazy(list, lane, n_listed, qs, pend_, posb_, flip, thtab, fcw, t, a.theta,
+                            adapt);
+          else
+            flush_list(list, lane, n_listed, qs, pend_, posb_, flip, quant, a.qc, a.qtop);
+        };
+        // LZ: lane c holds this round's settle threshold for a pair whose
+        // first word has c leading zeros, the float above theta_t + B_c
+        const float tl = LZ ? next_up(tht + bcl) : 0.0f;
         uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
         uint64_t posb = 0;     // list slot of each waiting pair, one byte each
         uint32_t total = 0;    // wave-uniform list length
   #pragma unroll
         for (int r = 0; r < QPL; ++r) {
           // a quad adds at most 2 * 64 entries: drain the list first if needed
-          if (r > 0 && total > (uint32_t)(kListCap - 2 * kWave)) {
-            flush_list(list, lane, total, qs, pend, posb, flip, quant, a.qc, a.qtop);
+          if (r > 0 && total > kCap - 2 * kWave) {
+            drain(total, pend, posb);
             total = 0;
             pend = 0;
             posb = 0;
           }
           const int j = ft + FT * r;
           // lanes past the last quad run the same code on a clamped index;
-          // their thresholds are -inf, so nothing of theirs is ever listed
+          // their margins are +inf (LZ) or their thresholds -inf, so nothing
+          // of theirs is ever listed
           const int jc = j < nq ? j : nq - 1;
           const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
                                           (uint32_t)(frame >> 32), key0, key1);
@@ -665,7 +763,12 @@ decode_kernel(DecodeArgs a) {
             const uint32_t wb = p ? wd.w3 : wd.w1;
             // m = (wa >> 8) + 1 = f 2^e.  clz(wa | 1) + 1 >= 24 - e (equal unless
             // wa >> 8 is 2^i - 1 or wa < 256), so the bound is never smaller
-            const float lim = __builtin_fmaf((float)__builtin_clz(wa | 1u), bound_c, bound_c);
+            const int lz = __builtin_clz(wa | 1u);
+            float lim = 0.0f, tc = 0.0f;
+            if (LZ)
+              tc = __int_as_float(__builtin_amdgcn_ds_bpermute(lz << 2, __float_as_int(tl)));
+            else
+              lim = __builtin_fmaf((float)lz, bound_c, bound_c);
             float avh[2], thh[2];
             bool settled = true;
   #pragma unroll
@@ -678,38 +781,51 @@ decode_kernel(DecodeArgs a) {
               // x_k y_k: flip the sign bit of y_k when x_k = -1 (exact)
               const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
               const float av = __builtin_fmaf(weff, Sf, xy);
-              // quantized: theta~_k = g(theta_k) (Sec. V-A); -inf stays -inf
-              const float th = (quant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
-              const float mg = av - th;
               avh[h] = av;
-              thh[h] = th;
-              // settled without a draw: a_k - theta_k >= qs * bound (no flip);
-              // with lim > 0, mg |mg| >= lim implies mg > 0 (NaN fails the test).
-              // Quantized: |g(q_k)| <= N_Q - 1 half steps bounds every draw.
-              settled = settled && (quant ? (mg >= a.qbound) : (mg * fabsf(mg) >= lim));
+              if (!LZ) {
+                // quantized: theta~_k = g(theta_k) (Sec. V-A); -inf stays -inf
+                const float th = (quant && thr[q] != -INFINITY) ? quant_half(thr[q], a.qc, a.qtop) : thr[q];
+                const float mg = av - th;
+                thh[h] = th;
+                // settled without a draw: a_k - theta_k >= qs * bound (no flip);
+                // with lim > 0, mg |mg| >= lim implies mg > 0 (NaN fails the test).
+                // Quantized: |g(q_k)| <= N_Q - 1 half steps bounds every draw.
+                settled = settled && (quant ? (mg >= a.qbound) : (mg * fabsf(mg) >= lim));
+              }
             }
+            // LZ: settled without a draw when both a_k >= theta_t + B_c; one
+            // comparison of the smaller (a NaN a_k never flips, whichever
+            // operand the minimum returns)
+            if (LZ) settled = fminf(avh[0], avh[1]) >= tc;
             const uint64_t bal = __ballot(!settled);
             if (!settled) {
-              const uint32_t ps = total + mask_rank(bal);
+              const uint32_t ps = (total + mask_rank(bal)) & 255u;  // < kCap <= 256
               const int q2 = 2 * r + p;
               pend |= 1u << q2;
               posb |= (uint64_t)ps << (8 * q2);
-              uint32_t *ent = list + kEntryWords * ps;
+              uint32_t *ent = list + kEW * ps;
               ent[0] = wa;
               ent[1] = wb;
               ent[2] = __float_as_uint(avh[0]);
               ent[3] = __float_as_uint(avh[1]);
-              ent[4] = __float_as_uint(thh[0]);
-              ent[5] = __float_as_uint(thh[1]);
+              if (LZ) {
+                // the pair's flip-count word (a lane past the last quad lists
+                // only under a NaN sigma, and its bits never flip)
+                ent[4] = (uint32_t)(2 * jc + p);
+              } else {
+                ent[4] = __float_as_uint(thh[0]);
+                ent[5] = __float_as_uint(thh[1]);
+              }
             }
             total += (uint32_t)__popcll(bal);
           }
         }
-        if (total) flush_list(list, lane, total, qs, pend, posb, flip, quant, a.qc, a.qtop);
+        if (total) drain(total, pend, posb);
       }
 
       // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
-      if (!QR && a.lambda != 1.0f && !single) {
+      if (LZ) tht = tht * a.lambda;  // theta_(t+1)
+      if (!LZ && !QR && a.lambda != 1.0f && !single) {
 #pragma unroll
         for (int q = 0; q < QPL * 4; ++q)
           if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
@@ -733,6 +849,7 @@ decode_kernel(DecodeArgs a) {
         const int q = __builtin_ctz(fl);
         fl &= fl - 1;
         const int k = 4 * (ft + FT * (q >> 2)) + (q & 3);
+        if (LZ && adapt) atomicAdd(&fcw[k >> 1], 1u << (16 * (k & 1)));
         const int c0 = REG ? k * a.dv : tab.col_ptr[k];
         const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
         for (int e = c0; e < c1; ++e) {
@@ -778,7 +895,7 @@ decode_kernel(DecodeArgs a) {
         // 3. every listed event moves u of its check's d_c bits, spread over
         //    all lanes of the frame
         frame_sync<WPF>();
-        const uint32_t nev = *(volatile uint32_t *)evc;
+        const uint32_t nev = __hip_atomic_load(evc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
         const uint32_t nup = listed * (uint32_t)a.dc;
         for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {

@@ -215,6 +215,22 @@ def test_edge_cases(torch_dev, case):
     assert_same(g, r, trace=True)
 
 
+@pytest.mark.parametrize("t_max", [5000, 9000])
+def test_long_adaptive_schedule(torch_dev, t_max):
+    """Adaptive thresholds over thousands of rounds: the base kernel's table of
+    theta lambda^u (T = 5000, fewer frames per workgroup to fit it) and the
+    multi-bit kernel that keeps thresholds in registers (T = 9000)."""
+    c = codes.named_code("C96")
+    sig = np.float32(channel.sigma_from_ebn0(1.0, c.rate))
+    y = channel.bpsk_awgn(60, c.n, sig, seed=64)
+    p = oracle.Params(w=0.75, theta=-0.9, lam=0.999, eta=0.95, ymax=2.5, t_max=t_max,
+                      smooth_window=64)
+    say("long schedule", t_max)
+    g, r = run_both(torch_dev, "C96", y, sig, p, seed=65)
+    assert (r.iters == t_max).any(), "some frame should use the whole schedule"
+    assert_same(g, r)
+
+
 def test_ragged_irregular_code(torch_dev):
     """n not a multiple of 4 or 8, irregular row and column degrees."""
     rng = np.random.Generator(np.random.PCG64(71))
