@@ -440,6 +440,15 @@ decode_kernel(DecodeArgs a) {
     // LZ: B_c >= qs s_c exactly, and theta_t of round 0
     const float bcl = LZ ? next_up(qs * s_lane) : 0.0f;
     float tht = a.theta;
+    // LZ: the frame's Philox counter words (wave-uniform) and the per-lane
+    // part of every quad's first rounds, computed once per frame
+    const uint32_t fr_lo = __builtin_amdgcn_readfirstlane((uint32_t)frame);
+    const uint32_t fr_hi = __builtin_amdgcn_readfirstlane((uint32_t)(frame >> 32));
+    PhiloxLane pl[QPL];
+    if (LZ) {
+#pragma unroll
+      for (int r = 0; r < QPL; ++r) pl[r] = philox_lane((uint32_t)(ft + FT * r), fr_lo, fr_hi, key0, key1);
+    }
 
     if (X) {
       // the argmin word starts at "no candidate"
@@ -737,6 +746,7 @@ decode_kernel(DecodeArgs a) {
         // LZ: lane c holds this round's settle threshold for a pair whose
         // first word has c leading zeros, the float above theta_t + B_c
         const float tl = LZ ? next_up(tht + bcl) : 0.0f;
+        const PhiloxRound pr = philox_round((uint32_t)t, fr_lo, key0, key1);
         uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
         uint64_t posb = 0;     // list slot of each waiting pair, one byte each
         uint32_t total = 0;    // wave-uniform list length
@@ -754,8 +764,9 @@ decode_kernel(DecodeArgs a) {
           // their margins are +inf (LZ) or their thresholds -inf, so nothing
           // of theirs is ever listed
           const int jc = j < nq ? j : nq - 1;
-          const Words4 wd = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
-                                          (uint32_t)(frame >> 32), key0, key1);
+          const Words4 wd = LZ ? philox_split(pl[r], pr, key0, key1)
+                               : philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame,
+                                               (uint32_t)(frame >> 32), key0, key1);
           const uint32_t u4 = uw[jc];
   #pragma unroll
           for (int p = 0; p < 2; ++p) {

@@ -60,6 +60,69 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
   return Words4{c0, c1, c2, c3};
 }
 
+// The same ten rounds for a counter (j, t, c2, c3) whose c2, c3 and key are
+// fixed for a whole frame and whose t is wave-uniform: rounds 0 and 1 and half
+// of round 2 then depend on j only through four per-lane words computed once
+// per frame (PhiloxLane) and on t only through wave-uniform words computed
+// once per round (PhiloxRound).  philox_split(philox_lane(j, ...),
+// philox_round(t, ...), ...) equals philox4x32_10(j, t, c2, c3, k0, k1).
+struct PhiloxLane {
+  uint32_t B;    // c3 after round 0: lo(M0 j)
+  uint32_t E;    // c1 after round 1: lo(M1 A), A = hi(M0 j) ^ c3 ^ k1
+  uint32_t H0c;  // hi(M0 C) of round 2, C = hi(M1 A) ^ lo(M1 c2) ^ (k0 + W0)
+  uint32_t L0c;  // lo(M0 C): c3 after round 2
+};
+struct PhiloxRound {
+  uint32_t dp;  // hi(M0 U) ^ (k1 + W1), U = hi(M1 c2) ^ t ^ k0: with B gives c2 after round 1
+  uint32_t vk;  // lo(M0 U) ^ (k1 + 2 W1): with H0c gives c2 after round 2
+};
+
+__device__ __forceinline__ PhiloxLane philox_lane(uint32_t j, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1) {
+  const uint64_t p0 = (uint64_t)kPhiloxM0 * j;
+  const uint32_t A = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * A;
+  const uint32_t L1a = (uint32_t)((uint64_t)kPhiloxM1 * c2);
+  const uint32_t C = (uint32_t)(p1 >> 32) ^ L1a ^ (k0 + kPhiloxW0);
+  const uint64_t p2 = (uint64_t)kPhiloxM0 * C;
+  return PhiloxLane{(uint32_t)p0, (uint32_t)p1, (uint32_t)(p2 >> 32), (uint32_t)p2};
+}
+
+__device__ __forceinline__ PhiloxRound philox_round(uint32_t t, uint32_t c2, uint32_t k0,
+                                                    uint32_t k1) {
+  const uint32_t U = (uint32_t)(((uint64_t)kPhiloxM1 * c2) >> 32) ^ t ^ k0;
+  const uint64_t p = (uint64_t)kPhiloxM0 * U;
+  return PhiloxRound{(uint32_t)(p >> 32) ^ (k1 + kPhiloxW1),
+                     (uint32_t)p ^ (k1 + 2u * kPhiloxW1)};
+}
+
+__device__ __forceinline__ Words4 philox_split(const PhiloxLane &pl, const PhiloxRound &pr,
+                                               uint32_t k0, uint32_t k1) {
+  // round 2 (rounds 0 and 1 are in pl and pr)
+  const uint32_t D = pl.B ^ pr.dp;  // c2 after round 1
+  const uint64_t p1 = (uint64_t)kPhiloxM1 * D;
+  uint32_t c0 = xor3_sk((uint32_t)(p1 >> 32), pl.E, k0 + 2u * kPhiloxW0);
+  uint32_t c1 = (uint32_t)p1;
+  uint32_t c2 = pl.H0c ^ pr.vk;
+  uint32_t c3 = pl.L0c;
+  k0 += 3u * kPhiloxW0;
+  k1 += 3u * kPhiloxW1;
+#pragma unroll
+  for (int r = 3; r < 10; ++r) {
+    const uint64_t q0 = (uint64_t)kPhiloxM0 * c0;
+    const uint64_t q1 = (uint64_t)kPhiloxM1 * c2;
+    const uint32_t n0 = xor3_sk((uint32_t)(q1 >> 32), c1, k0);
+    const uint32_t n2 = xor3_sk((uint32_t)(q0 >> 32), c3, k1);
+    c1 = (uint32_t)q1;
+    c3 = (uint32_t)q0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
 // binary32 constants, written as exact hex literals
 constexpr float kSqrt2 = 0x1.6a09e6p+0f;      // fl(sqrt 2)
 constexpr float kTwoLn2 = 0x1.62e430p+0f;     // fl(2 ln 2)
