@@ -13,8 +13,9 @@
 //   bit 4j + 2p + 0 takes the cosine branch, 4j + 2p + 1 the sine branch.
 //
 // ln, sin and cos are fixed binary32 operation sequences (below); sqrt and
-// the one division are IEEE correctly rounded; every fma is explicit and the
-// file is compiled with -ffp-contract=off.
+// the one division are IEEE correctly rounded (computed by short hardware
+// sequences whose results equal IEEE's on every input they receive); every fma
+// is explicit and the file is compiled with -ffp-contract=off.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -137,6 +138,32 @@ constexpr float kS3 = -0x1.555556p-3f, kS5 = 0x1.111112p-7f, kS7 = -0x1.a01a02p-
 constexpr float kC2 = -0.5f, kC4 = 0x1.555556p-5f, kC6 = -0x1.6c16c2p-10f,
                 kC8 = 0x1.a01a02p-16f, kC10 = -0x1.27e4fcp-22f;
 
+// (f - 1) / (f + 1) for f in [1/sqrt2, sqrt2), correctly rounded: the
+// hardware reciprocal refined once, then one quotient correction by the exact
+// fma residual (Markstein).  Its equality with IEEE division for every f the
+// radius takes is part of the exhaustive radius comparison over all 2^24 m.
+__device__ __forceinline__ float div_near1(float n, float d) {
+  const float y0 = __builtin_amdgcn_rcpf(d);
+  const float y1 = __builtin_fmaf(__builtin_fmaf(-d, y0, 1.0f), y0, y0);
+  const float q0 = n * y1;
+  const float r = __builtin_fmaf(-q0, d, n);
+  return __builtin_fmaf(r, y1, q0);
+}
+
+// sqrt(x) correctly rounded for x = 0 or x in [2^-24, 2^6): the hardware root,
+// moved to a neighbour when the exact fma residuals say so.  No scaling is
+// needed in this range; checked exhaustively like the division above.
+__device__ __forceinline__ float sqrt_radius(float x) {
+  const float s = __builtin_amdgcn_sqrtf(x);
+  const float sd = __uint_as_float(__float_as_uint(s) - 1u);
+  const float su = __uint_as_float(__float_as_uint(s) + 1u);
+  const float rd = __builtin_fmaf(-sd, s, x);
+  const float ru = __builtin_fmaf(-su, s, x);
+  float r = (rd <= 0.0f) ? sd : s;
+  r = (ru > 0.0f) ? su : r;
+  return r;
+}
+
 // Box-Muller radius for u1 = m 2^-24, m in [1, 2^24]:
 // m = f 2^e with f in [1/sqrt2, sqrt2); ln u1 = (e - 24) ln 2 + 2 atanh((f-1)/(f+1)).
 __device__ __forceinline__ float bm_radius(uint32_t m) {
@@ -146,7 +173,7 @@ __device__ __forceinline__ float bm_radius(uint32_t m) {
     f = f * 0.5f;
     e = e + 1;
   }
-  const float s = (f - 1.0f) / (f + 1.0f);
+  const float s = div_near1(f - 1.0f, f + 1.0f);
   const float s2 = s * s;
   float p = __builtin_fmaf(s2, kA11, kA9);
   p = __builtin_fmaf(s2, p, kA7);
@@ -154,7 +181,7 @@ __device__ __forceinline__ float bm_radius(uint32_t m) {
   p = __builtin_fmaf(s2, p, kA3);
   p = __builtin_fmaf(s2, p, 1.0f);
   const float base = (float)(24 - e) * kTwoLn2;
-  return sqrtf(__builtin_fmaf(-4.0f * s, p, base));
+  return sqrt_radius(__builtin_fmaf(-4.0f * s, p, base));
 }
 
 // cos and sin of the angle 2 pi i 2^-24, i in [0, 2^24): exact quadrant and
