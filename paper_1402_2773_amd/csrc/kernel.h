@@ -284,10 +284,11 @@ __device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32
 struct Tables {
   const uint16_t *col_idx, *row_idx, *row_ptr, *col_ptr;
   int dv, dc;
-  __device__ __forceinline__ int row_begin(int i) const { return dc ? i * dc : row_ptr[i]; }
-  __device__ __forceinline__ int row_end(int i) const { return dc ? i * dc + dc : row_ptr[i + 1]; }
-  __device__ __forceinline__ int col_begin(int k) const { return dv ? k * dv : col_ptr[k]; }
-  __device__ __forceinline__ int col_end(int k) const { return dv ? k * dv + dv : col_ptr[k + 1]; }
+  // (indices and degrees are below 2^16: 24-bit multiplies are exact)
+  __device__ __forceinline__ int row_begin(int i) const { return dc ? (int)__umul24(i, dc) : row_ptr[i]; }
+  __device__ __forceinline__ int row_end(int i) const { return dc ? (int)__umul24(i, dc) + dc : row_ptr[i + 1]; }
+  __device__ __forceinline__ int col_begin(int k) const { return dv ? (int)__umul24(k, dv) : col_ptr[k]; }
+  __device__ __forceinline__ int col_end(int k) const { return dv ? (int)__umul24(k, dv) + dv : col_ptr[k + 1]; }
 };
 
 // Decode kernel.  WPF wavefronts cooperate on one frame; each lane owns QPL
@@ -861,7 +862,7 @@ decode_kernel(DecodeArgs a) {
         fl &= fl - 1;
         const int k = 4 * (ft + FT * (q >> 2)) + (q & 3);
         if (LZ && adapt) atomicAdd(&fcw[k >> 1], 1u << (16 * (k & 1)));
-        const int c0 = REG ? k * a.dv : tab.col_ptr[k];
+        const int c0 = REG ? (int)__umul24(k, a.dv) : tab.col_ptr[k];
         const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
         for (int e = c0; e < c1; ++e) {
           const int i = tab.row_idx[e];
@@ -910,11 +911,13 @@ decode_kernel(DecodeArgs a) {
         const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
         const uint32_t nup = listed * (uint32_t)a.dc;
         for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {
-          const uint32_t e = (x * a.dc_recip) >> 20;    // x / d_c, exact here
+          // x / d_c, exact here; every product stays below 2^32 and its
+          // factors below 2^24
+          const uint32_t e = __umul24(x, a.dc_recip) >> 20;
           const uint32_t ev = evl[e];
           const int i = (int)(ev >> 1);
           const uint32_t d = (ev & 1u) ? 0xFFFFFFFFu : 1u;
-          const int k2 = tab.col_idx[i * a.dc + (int)(x - e * a.dc)];
+          const int k2 = tab.col_idx[(int)__umul24(i, a.dc) + (int)(x - __umul24(e, a.dc))];
           atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
         }
       }
