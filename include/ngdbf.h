@@ -186,7 +186,10 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
  * ngdbf_code_get_shape reports the shape that decodes with `params` use (host
  * int32 [3]); params may be NULL (the multi-bit binary32 decoder).  The
  * default differs between decoders: the extended ones (quantized, noise
- * reuse, single-bit, mode switching) take one quad per lane.
+ * reuse, single-bit with noise reuse, mode switching) take at most two quads
+ * per lane (more waves per frame); the base decoder, the packed quantized
+ * decoder with noise reuse and the single-bit decoder with per-bit draws take
+ * one wave per frame whenever the code fits in 1024 bits.
  * Not thread-safe against concurrent decodes of the same code.
  */
 int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,

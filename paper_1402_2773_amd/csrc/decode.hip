@@ -189,6 +189,7 @@ struct Layout {
   bool lists = true;    // per-wave Box-Muller lists (the settle-test path)
   bool packed = false;  // quantized multi-bit decoder with noise reuse in 16-bit lanes
   bool lazy = true;     // the base decoder: thresholds from a table and flip counts
+  bool bounded = false; // single-bit flips with per-bit draws (argmin by bounds)
   int thr_words = 0;    // the base decoder's table theta lambda^u, u = 0..T (float)
   int t_max = 0;
 };
@@ -269,10 +270,12 @@ Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
   L.trace = trace;
   L.ext = extended(p);
   L.stream_len = (p->noise_reuse && p->t_max > 0) ? c->n + p->t_max - 1 : 0;
-  // the lists serve multi-bit rounds with per-bit draws only
-  L.lists = !(p->noise_reuse || p->variant == NGDBF_SINGLE);
+  // the lists serve rounds with per-bit draws (the multi-bit settle test, the
+  // single-bit candidates)
+  L.lists = !p->noise_reuse;
   L.packed = packed_decoder(p);
   L.lazy = !L.ext;
+  L.bounded = p->variant == NGDBF_SINGLE && !p->noise_reuse;
   L.thr_words = (L.lazy && p->lambda != 1.0f) ? p->t_max + 1 : 0;
   L.t_max = p->t_max;
   return L;
@@ -307,8 +310,10 @@ int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
   const int nq = (c->n + 3) / 4;
   // the extended decoders keep more per-bit state: at most two quads per
   // lane (more waves per frame) keeps them out of register spills (the packed
-  // quantized decoder holds two bits per register and needs no such limit)
-  const bool few_quads = L.ext && !L.packed;
+  // quantized decoder holds two bits per register and needs no such limit;
+  // the single-bit decoder by bounds runs faster with one wave per frame,
+  // which saves its frame-wide reductions their barriers)
+  const bool few_quads = L.ext && !L.packed && !L.bounded;
   for (const auto &sh : kShapes) {
     if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
     if (nq <= 64 * sh[0] * sh[1]) {

@@ -212,6 +212,21 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
+__device__ __forceinline__ float wave_min_f32(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// a float as an unsigned key with the same order (-0 just below +0)
+__device__ __forceinline__ uint32_t ordered_key(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ordered_value(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -284,6 +299,39 @@ __device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32
   wave_sync();
 }
 
+// Single-bit rule by bounds: the listed pairs are those with a bit whose E_k
+// interval reaches the frame's least upper end; each lane transforms its
+// entries and keeps the least (E_k, k) key among their valid bits.
+__device__ __forceinline__ void flush_single(const uint32_t *list, int lane, uint32_t total,
+                                             float qs, bool quant, float qc, float qtop, int n,
+                                             uint64_t &best) {
+  wave_sync();
+  for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+    const uint32_t *ent = list + kEntryWords * e;
+    float z0, z1;
+    bm_pair(ent[0], ent[1], z0, z1);
+    const float av0 = __uint_as_float(ent[2]), av1 = __uint_as_float(ent[3]);
+    const int k0 = (int)ent[4];
+    float E0, E1;
+    if (quant) {
+      E0 = av0 + quant_half(qs * z0, qc, qtop);
+      E1 = av1 + quant_half(qs * z1, qc, qtop);
+    } else {
+      E0 = __builtin_fmaf(qs, z0, av0);
+      E1 = __builtin_fmaf(qs, z1, av1);
+    }
+    if (k0 < n && E0 == E0) {
+      const uint64_t key = argmin_key(E0, k0);
+      best = key < best ? key : best;
+    }
+    if (k0 + 1 < n && E1 == E1) {
+      const uint64_t key = argmin_key(E1, k0 + 1);
+      best = key < best ? key : best;
+    }
+  }
+  wave_sync();  // the list is refilled next
+}
+
 // Edges of check i (N(i)) and of bit k (M(k)) in the LDS tables.
 struct Tables {
   const uint16_t *col_idx, *row_idx, *row_ptr, *col_ptr;
@@ -331,8 +379,9 @@ struct Tables {
 // head (stop test, smoothing) below it and the Box-Muller list (few active
 // lanes, long transcendental chains) lowest, so that the SIMD's other waves
 // keep the vector ALU busy while a wave finishes its list (about 9% faster
-// on C1008 than equal priorities).  The packed quantized decoder raises its
-// syndrome update above its dense phase instead (about 2.5%).
+// on C1008 than equal priorities); the single-bit kernel's bound phase and
+// candidate list take the same levels.  The packed quantized decoder raises
+// its syndrome update above its dense phase instead (about 2.5%).
 //
 // EXT kernels add the other decoders of the paper (EXT = kExtMulti: the
 // multi-bit rule with quantization or noise reuse; kExtSingle: Step 3a;
@@ -406,7 +455,10 @@ decode_kernel(DecodeArgs a) {
   // LZ: lane c's radius bound sqrt(2 min(c + 1, 24) ln 2) with a relative
   // slack of 2e-5, which covers this computation's own rounding (< 3e-7) and
   // the computed radius's excess over the bound (< 1e-7)
-  const float s_lane = LZ ? sqrtf((float)(lane < 23 ? lane + 1 : 24) * 1.3862944f) * 1.00002f : 0.0f;
+  // (also the single-bit kernel's bound on |qs z_k|, BB)
+  constexpr bool BB = EXT == kExtSingle;
+  const float s_lane =
+      (LZ || BB) ? sqrtf((float)(lane < 23 ? lane + 1 : 24) * 1.3862944f) * 1.00002f : 0.0f;
   // kExtQuantReuse: the quantized thresholds theta~(u) = g(theta lambda^u)
   // (Sec. V-A) for every non-flip count u <= T, theta lambda^u by repeated
   // binary32 multiplication, once per workgroup
@@ -451,7 +503,7 @@ decode_kernel(DecodeArgs a) {
     // whose square underflows is never taken as settled
     const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
     // LZ: B_c >= qs s_c exactly, and theta_t of round 0
-    const float bcl = LZ ? next_up(qs * s_lane) : 0.0f;
+    const float bcl = (LZ || BB) ? next_up(qs * s_lane) : 0.0f;
     float tht = a.theta;
     // LZ: the frame's Philox counter words (wave-uniform) and the per-lane
     // part of every quad's first rounds, computed once per frame
@@ -466,7 +518,8 @@ decode_kernel(DecodeArgs a) {
     if (X) {
       // the argmin word starts at "no candidate"
       for (int i = ft; i < a.clear_words; i += FT)
-        slot[i] = (i == a.red_off || i == a.red_off + 1) ? 0xFFFFFFFFu : 0u;
+        slot[i] = (i == a.red_off || i == a.red_off + 1 || (BB && i == a.red_off + 2)) ? 0xFFFFFFFFu
+                                                                                       : 0u;
       if (QR) {
         // sample idx goes to R[L - 1 - idx] of each copy; R[L .. L + 2] = 0
         const int L = a.stream_len;
@@ -599,7 +652,7 @@ decode_kernel(DecodeArgs a) {
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
     for (;; ++t) {
-      if (LZ) __builtin_amdgcn_s_setprio(kPrioHead);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioHead);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedHead);
       const uint32_t unsat =
           __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
@@ -726,11 +779,94 @@ decode_kernel(DecodeArgs a) {
           }
           return best;
         };
+        // Step 3a by bounds (BB, per-bit draws): with c = clz(a | 1) of the
+        // pair's first word, |qs z_k| <= B_c (|g(qs z_k)| <= N_Q - 1 half
+        // steps, quantized), so E_k lies in [fl(a_k - B), fl(a_k + B)] (fma
+        // and sum round monotonically).  A bit whose lower end exceeds the
+        // least upper end U over the frame has E_k > U >= min E: it is neither
+        // the argmin nor tied with it.  Only pairs with a bit at or below U go
+        // through the transform.
+        auto bound_single = [&](auto quant_c) -> uint64_t {
+          constexpr bool kQuant = decltype(quant_c)::value;
+          __builtin_amdgcn_s_setprio(kPrioDense);
+          Words4 wq[QPL];
+          float avq[QPL * 4];
+          float ub = INFINITY;
+#pragma unroll
+          for (int r = 0; r < QPL; ++r) {
+            const int j = ft + FT * r;
+            const int jc = j < nq ? j : nq - 1;
+            wq[r] = philox4x32_10((uint32_t)j, (uint32_t)t, (uint32_t)frame, (uint32_t)(frame >> 32),
+                                  key0, key1);
+            const uint32_t u4 = uw[jc];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              const uint32_t wa = p ? wq[r].w2 : wq[r].w0;
+              const float bqp = kQuant ? a.qbound
+                                     : __int_as_float(__builtin_amdgcn_ds_bpermute(
+                                           __builtin_clz(wa | 1u) << 2, __float_as_int(bcl)));
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const int b = 2 * p + h;
+                const int q = 4 * r + b;
+                const float degf = REG ? (float)a.dv : (float)((deg4[r] >> (4 * b)) & 15u);
+                const float Sf = __builtin_fmaf(-2.0f, (float)((u4 >> (8 * b)) & 255u), degf);
+                const float xy = __uint_as_float(__float_as_uint(yv[q]) ^ (((xneg >> q) & 1u) << 31));
+                const float av = __builtin_fmaf(weff, Sf, xy);
+                avq[q] = av;
+                if ((vmask >> q) & 1u) ub = fminf(ub, av + bqp);
+              }
+            }
+          }
+          ub = wave_min_f32(ub);
+          if (WPF > 1) {
+            uint32_t *ubw = (uint32_t *)&red[1];
+            if (lane == 0) atomicMin(ubw, ordered_key(ub));
+            frame_sync<WPF>();
+            ub = ordered_value(__hip_atomic_load(ubw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            frame_sync<WPF>();
+            if (ft == 0) *ubw = 0xFFFFFFFFu;
+          }
+          uint64_t bl = ~0ull;
+          uint32_t total = 0;
+#pragma unroll
+          for (int r = 0; r < QPL; ++r) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              // a pair adds at most 64 entries
+              if (total > (uint32_t)(kListCap - kWave)) {
+                flush_single(list, lane, total, qs, kQuant, a.qc, a.qtop, n, bl);
+                total = 0;
+              }
+              const int q0 = 4 * r + 2 * p;
+              const uint32_t wa2 = p ? wq[r].w2 : wq[r].w0;
+              const float bqp = kQuant ? a.qbound
+                                     : __int_as_float(__builtin_amdgcn_ds_bpermute(
+                                           __builtin_clz(wa2 | 1u) << 2, __float_as_int(bcl)));
+              const float lo0 = avq[q0] - bqp, lo1 = avq[q0 + 1] - bqp;
+              const bool cand = (((vmask >> q0) & 1u) && lo0 <= ub) || (((vmask >> (q0 + 1)) & 1u) && lo1 <= ub);
+              const uint64_t bal = __ballot(cand);
+              if (cand) {
+                uint32_t *ent = list + kEntryWords * (total + mask_rank(bal));
+                ent[0] = p ? wq[r].w2 : wq[r].w0;
+                ent[1] = p ? wq[r].w3 : wq[r].w1;
+                ent[2] = __float_as_uint(avq[q0]);
+                ent[3] = __float_as_uint(avq[q0 + 1]);
+                ent[4] = (uint32_t)(4 * (ft + FT * r) + 2 * p);
+              }
+              total += (uint32_t)__popcll(bal);
+            }
+          }
+          __builtin_amdgcn_s_setprio(kPrioList);
+          if (total) flush_single(list, lane, total, qs, kQuant, a.qc, a.qtop, n, bl);
+          return bl;
+        };
         using T_ = std::true_type;
         using F_ = std::false_type;
         uint64_t best = ~0ull;
         if (single) {
           if (a.noise_reuse) best = quant ? direct(T_{}, T_{}, T_{}) : direct(T_{}, F_{}, T_{});
+          else if (BB) best = quant ? bound_single(T_{}) : bound_single(F_{});
           else best = quant ? direct(F_{}, T_{}, T_{}) : direct(F_{}, F_{}, T_{});
         } else {
           (void)(quant ? direct(T_{}, T_{}, F_{}) : direct(T_{}, F_{}, F_{}));
@@ -861,7 +997,7 @@ decode_kernel(DecodeArgs a) {
           if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
       }
       xneg ^= flip;
-      if (LZ) __builtin_amdgcn_s_setprio(kPrioSyndrome);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioSyndrome);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedSyndrome);
       if (TRACE) {
 #pragma unroll

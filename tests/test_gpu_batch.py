@@ -101,8 +101,11 @@ def test_shape_validation(torch_dev):
     assert ng.ngdbf_code_get_shape(dc.handle) == (1, 4, 16)
     # the extended decoders default to at most two quads per lane, except the
     # packed quantized one (whose stream leaves LDS for 8 frames per workgroup)
+    # and the single-bit one with per-bit draws
     ps = ng.Params(variant=ng.NGDBF_SINGLE).c(ng.NGDBF_Y_F32)
-    assert ng.ngdbf_code_get_shape(dc.handle, ps) == (2, 2, 1)
+    assert ng.ngdbf_code_get_shape(dc.handle, ps) == (1, 4, 16)
+    pr = ng.Params(variant=ng.NGDBF_SINGLE, noise_reuse=1).c(ng.NGDBF_Y_F32)
+    assert ng.ngdbf_code_get_shape(dc.handle, pr) == (2, 2, 1)
     pq = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75, t_max=300).c(ng.NGDBF_Y_F32)
     assert ng.ngdbf_code_get_shape(dc.handle, pq) == (1, 4, 8)
     dc.close()

@@ -91,6 +91,8 @@ CASES = {
     "reuse_fp32": P(noise_reuse=1, theta=-0.9, lam=0.98, eta=0.95, smooth_window=16),
     "quant4_single_reuse": P(variant=1, quant_bits=4, eta=0.9, ymax=1.75, noise_reuse=1),
     "quant1": P(quant_bits=1, theta=-0.5, eta=0.9, ymax=1.0),
+    "quant3_single": P(variant=1, quant_bits=3, eta=0.9, ymax=1.75),
+    "s_ngdbf_low_noise": P(variant=1, eta=0.05),
 }
 
 
@@ -121,7 +123,7 @@ SHAPES_1008 = [(1, 4, 2), (1, 4, 8), (2, 2, 1), (4, 1, 1), (8, 1, 1), (16, 1, 1)
 
 
 @pytest.mark.parametrize("shape", SHAPES_1008, ids=lambda s: "x".join(map(str, s)))
-@pytest.mark.parametrize("name", ["s_ngdbf", "mode_switch_noisy", "quant4_reuse"])
+@pytest.mark.parametrize("name", ["s_ngdbf", "quant3_single", "mode_switch_noisy", "quant4_reuse"])
 def test_variant_every_shape(torch_dev, name, shape):
     """The frame-wide reductions (argmin, objective) across 1..16 waves."""
     c = codes.named_code("C1008")
