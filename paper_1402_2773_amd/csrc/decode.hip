@@ -227,8 +227,9 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
       w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
   } else {
     if (L.lazy) {
+      // flip counts of every bit of every quad: 8-bit if T <= 255, else 16-bit
       p.fc_off = w;
-      w += 2 * ((c->n + 3) / 4);  // two 16-bit counts per word, every pair of every quad
+      w += (L.t_max <= 255 ? 1 : 2) * ((c->n + 3) / 4);
     }
     p.clear_words = w;
   }
@@ -236,14 +237,20 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
   return p;
 }
 
-// LDS words: code tables | [threshold table] | frame slots | wave lists
-int qtab_offset(const ngdbf_code *c) { return (c->table_words + 1) & ~1; }
-int slots_offset(const ngdbf_code *c, const Layout &L) {
-  return qtab_offset(c) + ((packed_table_words(L) + L.thr_words + 1) & ~1);
+// The base kernel with four or more waves per frame reads the code tables
+// from global memory (the kernel's TG); every other instance stages them.
+bool tables_in_lds(const Layout &L, const Shape &sh) { return !(L.lazy && sh.wpf >= 4); }
+
+// LDS words: [code tables] | [threshold table] | frame slots | wave lists
+int qtab_offset(const ngdbf_code *c, const Layout &L, const Shape &sh) {
+  return tables_in_lds(L, sh) ? (c->table_words + 1) & ~1 : 0;
+}
+int slots_offset(const ngdbf_code *c, const Layout &L, const Shape &sh) {
+  return qtab_offset(c, L, sh) + ((packed_table_words(L) + L.thr_words + 1) & ~1);
 }
 
 size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
-  return ((size_t)slots_offset(c, L) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
+  return ((size_t)slots_offset(c, L, sh) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
           (size_t)(sh.block() / 64) * list_words(L)) * 4;
 }
 
@@ -442,10 +449,11 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   const SlotPlan plan = slot_plan(code, L);
   a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
   a.slot_words = plan.slot_words;
-  a.slots_off = slots_offset(code, L);
-  a.qtab_off = qtab_offset(code);
-  a.thr_off = qtab_offset(code);
+  a.slots_off = slots_offset(code, L, sh);
+  a.qtab_off = qtab_offset(code, L, sh);
+  a.thr_off = qtab_offset(code, L, sh);
   a.fc_off = plan.fc_off;
+  a.fc_bytes = p->t_max <= 255 ? 1 : 0;
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;

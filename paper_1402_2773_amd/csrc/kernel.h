@@ -122,6 +122,7 @@ struct DecodeArgs {
   // 2i and 2i + 1; slot word offset)
   int32_t thr_off;
   int32_t fc_off;
+  int32_t fc_bytes;     // 1: one 8-bit count per bit (T <= 255), 0: 16-bit counts
 };
 
 template <int YFMT>
@@ -272,7 +273,7 @@ __device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t to
 __device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32_t total, float qs,
                                                 uint32_t pend, uint64_t posb, uint32_t &flip,
                                                 const float *thtab, const uint32_t *fcw, int t,
-                                                float theta, bool adapt) {
+                                                float theta, bool adapt, bool fc_bytes) {
   wave_sync();
   for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
     uint32_t *ent = list + kEntryWordsLazy * e;
@@ -282,9 +283,20 @@ __device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32
     const float E1 = __builtin_fmaf(qs, z1, __uint_as_float(ent[3]));
     float th0 = theta, th1 = theta;
     if (adapt) {
-      const uint32_t fc = fcw[ent[4]];
-      th0 = thtab[t - (int)(fc & 0xFFFFu)];
-      th1 = thtab[t - (int)(fc >> 16)];
+      // the pair's flip counts (bits k0, k0 + 1; k0 even)
+      const uint32_t k0 = ent[4];
+      int f0, f1;
+      if (fc_bytes) {
+        const uint32_t fc = fcw[k0 >> 2] >> (8 * (k0 & 3u));
+        f0 = (int)(fc & 0xFFu);
+        f1 = (int)((fc >> 8) & 0xFFu);
+      } else {
+        const uint32_t fc = fcw[k0 >> 1];
+        f0 = (int)(fc & 0xFFFFu);
+        f1 = (int)(fc >> 16);
+      }
+      th0 = thtab[t - f0];
+      th1 = thtab[t - f1];
     }
     ent[0] = (E0 < th0 ? 1u : 0u) | (E1 < th1 ? 2u : 0u);
   }
@@ -409,9 +421,13 @@ decode_kernel(DecodeArgs a) {
   const int nbytes = (n + 7) >> 3;
   const int T = a.t_max, W = a.smooth_window;
 
-  // stage the code tables once per workgroup
-  for (int i = tid; i < a.table_words; i += blockDim.x) lds[i] = a.tables[i];
-  const uint16_t *t16 = (const uint16_t *)lds;
+  // stage the code tables once per workgroup; the base kernel with four or
+  // more waves per frame reads them from global memory through the caches
+  // instead (a frame is a workgroup there, and the LDS goes to more of them)
+  constexpr bool TG = EXT == kExtNone && WPF >= 4;
+  if (!TG)
+    for (int i = tid; i < a.table_words; i += blockDim.x) lds[i] = a.tables[i];
+  const uint16_t *t16 = TG ? (const uint16_t *)a.tables : (const uint16_t *)lds;
   Tables tab;
   tab.col_idx = t16;
   tab.row_idx = t16 + a.off_row;
@@ -428,7 +444,7 @@ decode_kernel(DecodeArgs a) {
   uint32_t *evn = cnt + 1;                 // [2] events listed (rounds alternate)
   uint32_t *tw = evn + 2;                  // [sw_words] checks toggled this round
   uint32_t *evl = tw + a.sw_words;         // [kEventCap] toggle events
-  uint32_t *fcw = slot + a.fc_off;         // LZ: flip counts, two bits per word
+  uint32_t *fcw = slot + a.fc_off;         // LZ: flip counts, four or two bits per word
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
@@ -892,7 +908,7 @@ decode_kernel(DecodeArgs a) {
         auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
           if (LZ)
             flush_list_lazy(list, lane, n_listed, qs, pend_, posb_, flip, thtab, fcw, t, a.theta,
-                            adapt);
+                            adapt, a.fc_bytes != 0);
           else
             flush_list(list, lane, n_listed, qs, pend_, posb_, flip, quant, a.qc, a.qtop);
         };
@@ -974,9 +990,9 @@ decode_kernel(DecodeArgs a) {
               ent[2] = __float_as_uint(avh[0]);
               ent[3] = __float_as_uint(avh[1]);
               if (LZ) {
-                // the pair's flip-count word (a lane past the last quad lists
-                // only under a NaN sigma, and its bits never flip)
-                ent[4] = (uint32_t)(2 * jc + p);
+                // the pair's first bit, for its flip counts (a lane past the
+                // last quad lists only under a NaN sigma; its bits never flip)
+                ent[4] = (uint32_t)(4 * jc + 2 * p);
               } else {
                 ent[4] = __float_as_uint(thh[0]);
                 ent[5] = __float_as_uint(thh[1]);
@@ -1017,7 +1033,12 @@ decode_kernel(DecodeArgs a) {
         const int q = __builtin_ctz(fl);
         fl &= fl - 1;
         const int k = 4 * (ft + FT * (q >> 2)) + (q & 3);
-        if (LZ && adapt) atomicAdd(&fcw[k >> 1], 1u << (16 * (k & 1)));
+        if (LZ && adapt) {
+          if (a.fc_bytes)
+            atomicAdd(&fcw[k >> 2], 1u << (8 * (k & 3)));
+          else
+            atomicAdd(&fcw[k >> 1], 1u << (16 * (k & 1)));
+        }
         const int c0 = REG ? (int)__umul24(k, a.dv) : tab.col_ptr[k];
         const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
         for (int e = c0; e < c1; ++e) {

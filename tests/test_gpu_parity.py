@@ -215,6 +215,26 @@ def test_edge_cases(torch_dev, case):
     assert_same(g, r, trace=True)
 
 
+@pytest.mark.parametrize("shape", [(1, 4, 8), (2, 2, 1), (4, 1, 1), (8, 1, 1), (16, 1, 1)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("t_max", [200, 300])
+def test_base_kernel_every_shape(torch_dev, shape, t_max):
+    """The base kernel on every launch shape that holds C1008: code tables in
+    LDS (one and two waves per frame) or read from global memory (four or more
+    waves), 8-bit (T <= 255) or 16-bit flip counts."""
+    c, dc = dev_code("C1008")
+    sig = np.float32(channel.sigma_from_ebn0(2.5, c.rate))
+    y = channel.bpsk_awgn(150, c.n, sig, seed=66)
+    p = oracle.Params(w=0.75, theta=-0.9, lam=0.97, eta=0.95, ymax=2.5, t_max=t_max, smooth_window=64)
+    say("base shape", shape, t_max)
+    ng.ngdbf_code_set_shape(dc.handle, *shape)
+    try:
+        g, r = run_both(torch_dev, "C1008", y, sig, p, seed=67, trace=True)
+    finally:
+        ng.ngdbf_code_set_shape(dc.handle, 0, 0, 0)
+    assert_same(g, r, trace=True)
+
+
 @pytest.mark.parametrize("t_max", [5000, 9000])
 def test_long_adaptive_schedule(torch_dev, t_max):
     """Adaptive thresholds over thousands of rounds: the base kernel's table of
