@@ -405,8 +405,18 @@ struct Tables {
 // theta_k through g, all in half-step units, so E_k is an exact small
 // integer) and the noise chain of Sec. V-B (the frame's n + T - 1 samples are
 // drawn once into LDS; bit k reads element n - 1 + t - k in round t).
+
+// Occupancy target: four waves per SIMD; the base kernel with four or more
+// waves per frame (code tables outside the LDS) aims higher when each lane
+// holds fewer quads.
+template <int WPF, int QPL, int EXT>
+constexpr int waves_per_simd() {
+  return (EXT == kExtNone && WPF >= 4) ? (QPL == 1 ? 8 : (QPL == 2 ? 6 : 4)) : 4;
+}
+
 template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, int EXT>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(waves_per_simd<WPF, QPL, EXT>())))
 decode_kernel(DecodeArgs a) {
   constexpr bool X = EXT != kExtNone;
   extern __shared__ uint32_t lds[];
