@@ -78,12 +78,10 @@ WORKLOADS = {
 }
 DEFAULT = "c1008_sm_3.5dB"
 
-# launch shapes (waves per frame, quads per lane, frames per workgroup) chosen
-# by timing for workloads whose default shape is slower (timed per shape on the GPU)
-WORKLOAD_SHAPES = {
-    "c2048_plain_4.5dB_f32": (4, 2, 1), "c2048_plain_4.5dB_i8": (4, 2, 1),
-    "c2048_tuned_4.5dB_f32": (4, 2, 1), "c2048_tuned_4.5dB_i8": (4, 2, 1),
-}
+# launch shapes (waves per frame, quads per lane, frames per workgroup) for
+# workloads whose default shape is slower (none at present: the library's
+# default is the fastest timed shape for every workload here)
+WORKLOAD_SHAPES = {}
 
 # Batched multi-code workload: the four codes in frame proportions 4:2:1:1,
 # per-frame Eb/N0 uniform in [2, 5] dB, per-code parameters as above

@@ -321,8 +321,13 @@ int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
   // the single-bit decoder by bounds runs faster with one wave per frame,
   // which saves its frame-wide reductions their barriers)
   const bool few_quads = L.ext && !L.packed && !L.bounded;
+  // the base kernel's frames of more than one wave take four or more waves
+  // (code tables outside the LDS, more workgroups per CU: C2048 at (4, 2)
+  // runs twice as fast as at (2, 4))
+  const bool wide = L.lazy && nq > 64 * 4;
   for (const auto &sh : kShapes) {
     if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
+    if (wide && sh[0] < 4) continue;
     if (nq <= 64 * sh[0] * sh[1]) {
       Shape cand{sh[0], sh[1], sh[0] == 1 ? 16 : 1};
       while (check_shape(c, cand, L) != NGDBF_OK && cand.fpb > 1) cand.fpb /= 2;
