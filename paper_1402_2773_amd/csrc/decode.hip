@@ -194,8 +194,9 @@ struct Layout {
   int t_max = 0;
 };
 
-// samples per shifted copy of the packed decoder's reversed stream
-int packed_stream_lr(const Layout &L) { return L.stream_len > 0 ? (L.stream_len + 3 + 3) & ~3 : 0; }
+// int16 samples in the packed decoder's reversed stream: L, then zeros up to a
+// multiple of four covering the last quad's two 8-byte words (L + 7)
+int packed_stream_lr(const Layout &L) { return L.stream_len > 0 ? (L.stream_len + 8 + 3) & ~3 : 0; }
 // words of the packed decoder's threshold table theta~(u), u = 0..T (int16)
 int packed_table_words(const Layout &L) { return L.packed ? ((L.t_max + 2) / 2 + 1) & ~1 : 0; }
 
@@ -222,7 +223,7 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
     p.stream_off = w;
     p.clear_words = w;
     if (L.packed)
-      w += 2 * packed_stream_lr(L);       // four shifted int16 copies
+      w += packed_stream_lr(L) / 2;       // one int16 row
     else
       w += 4 * ((L.stream_len + 3) / 4);  // four interleaved rows
   } else {

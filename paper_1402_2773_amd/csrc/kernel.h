@@ -116,7 +116,7 @@ struct DecodeArgs {
   int32_t list_words;   // Box-Muller list words per wave (0 when no list is used)
   int32_t clear_words;  // slot words cleared per frame (the stream is rewritten)
   int32_t qtab_off;     // kExtQuantReuse: LDS word offset of theta~(u), u = 0..T (int16)
-  int32_t stream_lr;    // kExtQuantReuse: int16 samples per shifted copy of the stream
+  int32_t stream_lr;    // kExtQuantReuse: int16 samples in the stream's row (a multiple of 4)
   // base decoder (kExtNone): theta lambda^u for u = 0..T (float, LDS word
   // offset) and the per-frame flip counts (two 16-bit counts per word: bits
   // 2i and 2i + 1; slot word offset)
@@ -496,9 +496,9 @@ decode_kernel(DecodeArgs a) {
       qtab[u] = (int16_t)quant_half(th, a.qc, a.qtop);
     }
   }
-  // kExtQuantReuse: the stream reversed, R[i] = g(q) of element L - 1 - i, in
-  // four copies shifted by 0..3 samples, so that a lane reads its quad's four
-  // samples as one aligned 8-byte word in every round
+  // kExtQuantReuse: the stream reversed, R[i] = g(q) of element L - 1 - i
+  // (int16), zero from i = L to the row's end; a lane reads its quad's four
+  // samples from two aligned 8-byte words, shifted by the round's phase
   int16_t *qstream = (int16_t *)(slot + a.stream_off);
   __syncthreads();
 
@@ -547,7 +547,7 @@ decode_kernel(DecodeArgs a) {
         slot[i] = (i == a.red_off || i == a.red_off + 1 || (BB && i == a.red_off + 2)) ? 0xFFFFFFFFu
                                                                                        : 0u;
       if (QR) {
-        // sample idx goes to R[L - 1 - idx] of each copy; R[L .. L + 2] = 0
+        // sample idx goes to R[L - 1 - idx]; R[L .. stream_lr - 1] = 0
         const int L = a.stream_len;
         const int nsq = (L + 3) >> 2;
         for (int jq = ft; jq < nsq; jq += FT) {
@@ -561,19 +561,11 @@ decode_kernel(DecodeArgs a) {
             const int idx = 4 * jq + b;
             if (idx < L) {
               const int i = L - 1 - idx;
-              const int16_t v = (int16_t)quant_half(qs * z[b], a.qc, a.qtop);
-#pragma unroll
-              for (int ph = 0; ph < 4; ++ph)
-                if (i >= ph) qstream[ph * a.stream_lr + (i - ph)] = v;
+              qstream[i] = (int16_t)quant_half(qs * z[b], a.qc, a.qtop);
             }
           }
         }
-        if (ft < 3 && L > 0) {
-          const int i = L + ft;
-#pragma unroll
-          for (int ph = 0; ph < 4; ++ph)
-            if (i >= ph) qstream[ph * a.stream_lr + (i - ph)] = 0;
-        }
+        for (int i = L + ft; i < a.stream_lr; i += FT) qstream[i] = 0;
       } else if (a.noise_reuse) {
         // the shift-register chain (Sec. V-B): sample j of the frame's stream
         // is draw j & 3 of quad j >> 2 under the iteration word 0xFFFFFFFF
@@ -727,9 +719,22 @@ decode_kernel(DecodeArgs a) {
           const int j = ft + FT * r;
           const int jc = j < nq ? j : nq - 1;
           const uint32_t u4 = uw[jc];
+          // samples R[sidx .. sidx + 3] from the aligned words at sidx - ph and
+          // sidx - ph + 4 (the phase ph = sbase & 3 is the same for every lane)
           const int sidx = sbase + 4 * jc;
-          const int ph = sidx & 3;
-          const uint2 sv = *(const uint2 *)(qstream + ph * a.stream_lr + (sidx - ph));
+          const int ph = sbase & 3;
+          const uint2 *wp = (const uint2 *)(qstream + (sidx - ph));
+          const uint2 w0 = wp[0];
+          uint2 sv = w0;
+          if (ph != 0) {
+            const uint2 w1 = wp[1];
+            if (ph == 1)
+              sv = uint2{__builtin_amdgcn_alignbyte(w0.y, w0.x, 2u), __builtin_amdgcn_alignbyte(w1.x, w0.y, 2u)};
+            else if (ph == 2)
+              sv = uint2{w0.y, w1.x};
+            else
+              sv = uint2{__builtin_amdgcn_alignbyte(w1.x, w0.y, 2u), __builtin_amdgcn_alignbyte(w1.y, w1.x, 2u)};
+          }
           uint32_t fq = 0;
 #pragma unroll
           for (int pp = 0; pp < 2; ++pp) {

@@ -100,14 +100,16 @@ def test_shape_validation(torch_dev):
     ng.ngdbf_code_set_shape(dc.handle, 0, 0, 0)
     assert ng.ngdbf_code_get_shape(dc.handle) == (1, 4, 16)
     # the extended decoders default to at most two quads per lane, except the
-    # packed quantized one (whose stream leaves LDS for 8 frames per workgroup)
-    # and the single-bit one with per-bit draws
+    # packed quantized one and the single-bit one with per-bit draws
     ps = ng.Params(variant=ng.NGDBF_SINGLE).c(ng.NGDBF_Y_F32)
     assert ng.ngdbf_code_get_shape(dc.handle, ps) == (1, 4, 16)
     pr = ng.Params(variant=ng.NGDBF_SINGLE, noise_reuse=1).c(ng.NGDBF_Y_F32)
     assert ng.ngdbf_code_get_shape(dc.handle, pr) == (2, 2, 1)
     pq = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75, t_max=300).c(ng.NGDBF_Y_F32)
-    assert ng.ngdbf_code_get_shape(dc.handle, pq) == (1, 4, 8)
+    assert ng.ngdbf_code_get_shape(dc.handle, pq) == (1, 4, 16)
+    # a long schedule's stream leaves LDS for fewer frames per workgroup
+    pl = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75, t_max=4000).c(ng.NGDBF_Y_F32)
+    assert ng.ngdbf_code_get_shape(dc.handle, pl)[:2] == (1, 4)
     dc.close()
 
 
