@@ -598,6 +598,22 @@ def main() -> int:
                      "kernel": "decode_kernel", "kernel_ms": kernel_s * 1e3,
                      "hbm_achieved_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS},
     }
+    # the exact noise skip, counted in one more (untimed) decode: pairs of bits
+    # whose decision the radius bound fixed without a Box-Muller transform
+    extended = (params.get("variant", 0) != 0 or params.get("quant_bits", 0) != 0
+                or params.get("noise_reuse", 0) != 0)
+    if not extended:
+        counters = torch.zeros(2, dtype=torch.int64, device="cuda")
+        ng.ngdbf_code_set_stats(dev_code.handle, counters)
+        ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ng.ngdbf_code_set_stats(dev_code.handle, None)
+        evaluated, transformed = (int(v) for v in counters.cpu().tolist())
+        result["gaussian_draws"] = {
+            "defined": 2 * evaluated, "transformed": 2 * transformed,
+            "skipped_frac": 1.0 - transformed / evaluated if evaluated else None,
+            "what": "draws the method defines (one per bit and round) and those the "
+                    "kernel computed: the rest could not change a decision"}
     if not args.no_cpu_baseline:
         y_host = y[: min(frames, 1 << 16)].cpu().numpy()
         result["cpu_baseline"] = cpu_baseline(code, y_host, sigma, params, seed, args.cpu_seconds)

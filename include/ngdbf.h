@@ -198,6 +198,22 @@ int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
                          int32_t shape[3]);
 
 /*
+ * ngdbf_code_set_stats -- attach (or, with NULL, detach) device counters to a
+ * code for instrumentation of the exact noise skip of the multi-bit binary32
+ * decoder (the settle test: a pair of bits whose decision the bound on the
+ * Box-Muller radius fixes needs no transform; Sec. III-C draws every q_k).
+ *   counters : dev uint64 [2], or NULL.  While attached, every decode of this
+ *              code by that decoder adds to counters[0] the bit pairs it
+ *              evaluated (ceil(n / 2) per frame and round) and to counters[1]
+ *              the pairs it transformed; the caller zeroes them.  Other
+ *              decoders leave them unchanged.
+ * Adds one counter update per frame and wave; results are unchanged.  Not
+ * thread-safe against concurrent decodes of the same code.
+ * Errors: NGDBF_EINVAL (code is NULL).
+ */
+int ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters);
+
+/*
  * ngdbf_autotune -- time every built launch shape that fits the code on the
  * given sample (same arguments as ngdbf_decode; outputs go to scratch the
  * call allocates and frees) and keep the fastest on the code handle.  The

@@ -24,7 +24,7 @@ NGDBF_Y_I8 = 1
 #: names of the C entry points (include/ngdbf.h)
 ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "ngdbf_decode",
                  "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_code_set_shape",
-                 "ngdbf_code_get_shape", "ngdbf_autotune", "ngdbf_decode_batch",
+                 "ngdbf_code_get_shape", "ngdbf_code_set_stats", "ngdbf_autotune", "ngdbf_decode_batch",
                  "ngdbf_decode_segments", "ngdbf_server_create", "ngdbf_server_destroy",
                  "ngdbf_server_pools", "ngdbf_server_admit", "ngdbf_server_commit",
                  "ngdbf_server_pump", "ngdbf_server_poll", "ngdbf_server_release",
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_noise_probe.argtypes = [I32, U32, U32, U64, U64, U32, P, P, P]
         L.ngdbf_code_set_shape.argtypes = [P, I32, I32, I32]
         L.ngdbf_code_get_shape.argtypes = [P, ctypes.POINTER(ngdbf_params), P]
+        L.ngdbf_code_set_stats.argtypes = [P, P]
         L.ngdbf_autotune.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, P, P, P]
         L.ngdbf_decode_batch.argtypes = [ctypes.POINTER(ngdbf_job), I32, P]
         L.ngdbf_decode_segments.argtypes = [P, P, P, F, I64, ctypes.POINTER(ngdbf_params), P,
@@ -212,6 +213,11 @@ def ngdbf_code_get_shape(code, params: Optional[ngdbf_params] = None):
     _check(lib().ngdbf_code_get_shape(code, ctypes.byref(params) if params is not None else None,
                                       shape))
     return tuple(shape)
+
+
+def ngdbf_code_set_stats(code, counters) -> None:
+    """Attach a device uint64 [2] tensor (or None) as the settle-test counters."""
+    _check(lib().ngdbf_code_set_stats(code, _addr(counters)))
 
 
 def ngdbf_autotune(code, y, n_frames: int, sigma, sigma_scalar: float, params: ngdbf_params,

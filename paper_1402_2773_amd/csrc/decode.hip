@@ -97,6 +97,7 @@ struct ngdbf_code {
   int32_t dv, dc;      // uniform degrees (0 if irregular)
   int32_t max_col_deg, max_row_deg;
   int32_t shape[3];    // fixed launch shape (waves/frame, quads/lane, frames/block), 0 = default
+  uint64_t *stats;     // device counters of the settle test, or NULL
 };
 
 namespace {
@@ -460,6 +461,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.thr_off = qtab_offset(code, L, sh);
   a.fc_off = plan.fc_off;
   a.fc_bytes = p->t_max <= 255 ? 1 : 0;
+  a.stats = code->stats;
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;
@@ -744,6 +746,12 @@ int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quad
   code->shape[0] = sh.wpf;
   code->shape[1] = sh.qpl;
   code->shape[2] = sh.fpb;
+  return ok();
+}
+
+int ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters) {
+  if (!code) return fail(NGDBF_EINVAL, "code is NULL");
+  code->stats = counters;
   return ok();
 }
 

@@ -123,6 +123,7 @@ struct DecodeArgs {
   int32_t thr_off;
   int32_t fc_off;
   int32_t fc_bytes;     // 1: one 8-bit count per bit (T <= 255), 0: 16-bit counts
+  uint64_t *stats;      // base kernel: [pairs evaluated, pairs transformed], or null
 };
 
 template <int YFMT>
@@ -666,6 +667,7 @@ decode_kernel(DecodeArgs a) {
 
     int t = 0;
     int converged = 0;
+    uint32_t listed_frame = 0;  // LZ with stats: pairs this wave transformed
     bool mu = true;        // mode switching: multi-bit rounds until f drops
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
@@ -921,6 +923,7 @@ decode_kernel(DecodeArgs a) {
         constexpr uint32_t kCap = LZ ? (uint32_t)kListCapLazy : (uint32_t)kListCap;
         constexpr int kEW = LZ ? kEntryWordsLazy : kEntryWords;
         auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
+          listed_frame += n_listed;
           if (LZ)
             flush_list_lazy(list, lane, n_listed, qs, pend_, posb_, flip, thtab, fcw, t, a.theta,
                             adapt, a.fc_bytes != 0);
@@ -1122,6 +1125,12 @@ decode_kernel(DecodeArgs a) {
         for (int i = ft; i < a.xw_words; i += FT) fw[i] = 0u;
         frame_sync<WPF>();
       }
+    }
+
+    if (LZ && a.stats) {
+      if (lane == 0) atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)listed_frame);
+      if (ft == 0)
+        atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)t * (unsigned long long)((n + 1) / 2));
     }
 
     // output: x, or sign(X) when T was reached with smoothing on (Sec. III-E)

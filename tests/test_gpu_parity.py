@@ -235,6 +235,30 @@ def test_base_kernel_every_shape(torch_dev, shape, t_max):
     assert_same(g, r, trace=True)
 
 
+def test_settle_statistics(torch_dev):
+    """The settle-test counters: every round of every frame evaluates ceil(n/2)
+    pairs, a minority of them is transformed, and the decode is unchanged."""
+    torch = torch_dev
+    c, dc = dev_code("C1008")
+    sig = np.float32(channel.sigma_from_ebn0(3.5, c.rate))
+    y = channel.bpsk_awgn(400, c.n, sig, seed=68)
+    p = p_heur(3.5)
+    counters = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ng.ngdbf_code_set_stats(dc.handle, counters)
+    try:
+        g, r = run_both(torch, "C1008", y, sig, p, seed=69)
+    finally:
+        ng.ngdbf_code_set_stats(dc.handle, None)
+    assert_same(g, r)
+    evaluated, transformed = counters.cpu().tolist()
+    say("pairs evaluated", evaluated, "transformed", transformed)
+    assert evaluated == int(r.iters.astype(np.int64).sum()) * ((c.n + 1) // 2)
+    assert 0 < transformed < evaluated // 4
+    # detached: the counters stay as they are
+    run_both(torch, "C1008", y[:8], sig, p, seed=69)
+    assert counters.cpu().tolist() == [evaluated, transformed]
+
+
 @pytest.mark.parametrize("t_max", [5000, 9000])
 def test_long_adaptive_schedule(torch_dev, t_max):
     """Adaptive thresholds over thousands of rounds: the base kernel's table of
