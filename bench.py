@@ -600,9 +600,9 @@ def main() -> int:
     }
     # the exact noise skip, counted in one more (untimed) decode: pairs of bits
     # whose decision the radius bound fixed without a Box-Muller transform
-    extended = (params.get("variant", 0) != 0 or params.get("quant_bits", 0) != 0
-                or params.get("noise_reuse", 0) != 0)
-    if not extended:
+    counted = (params.get("variant", 0) == 0 and params.get("quant_bits", 0) == 0
+               and params.get("noise_reuse", 0) == 0)
+    if counted:
         counters = torch.zeros(2, dtype=torch.int64, device="cuda")
         ng.ngdbf_code_set_stats(dev_code.handle, counters)
         ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)

@@ -200,14 +200,15 @@ int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
 /*
  * ngdbf_code_set_stats -- attach (or, with NULL, detach) device counters to a
  * code for instrumentation of the exact noise skip of the multi-bit binary32
- * decoder (the settle test: a pair of bits whose decision the bound on the
- * Box-Muller radius fixes needs no transform; Sec. III-C draws every q_k).
+ * decoder (Sec. III-C draws every q_k; a pair of bits whose decision the bound
+ * on the Box-Muller radius fixes needs no transform).
  *   counters : dev uint64 [2], or NULL.  While attached, every decode of this
  *              code by that decoder adds to counters[0] the bit pairs it
  *              evaluated (ceil(n / 2) per frame and round) and to counters[1]
  *              the pairs it transformed; the caller zeroes them.  Other
  *              decoders leave them unchanged.
- * Adds one counter update per frame and wave; results are unchanged.  Not
+ * While attached, every wave updates the counters once per round (slower: for
+ * instrumentation, not for timed runs); results are unchanged.  Not
  * thread-safe against concurrent decodes of the same code.
  * Errors: NGDBF_EINVAL (code is NULL).
  */

@@ -667,7 +667,6 @@ decode_kernel(DecodeArgs a) {
 
     int t = 0;
     int converged = 0;
-    uint32_t listed_frame = 0;  // LZ with stats: pairs this wave transformed
     bool mu = true;        // mode switching: multi-bit rounds until f drops
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
@@ -923,7 +922,7 @@ decode_kernel(DecodeArgs a) {
         constexpr uint32_t kCap = LZ ? (uint32_t)kListCapLazy : (uint32_t)kListCap;
         constexpr int kEW = LZ ? kEntryWordsLazy : kEntryWords;
         auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
-          listed_frame += n_listed;
+          if (LZ && a.stats && lane == 0) atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)n_listed);
           if (LZ)
             flush_list_lazy(list, lane, n_listed, qs, pend_, posb_, flip, thtab, fcw, t, a.theta,
                             adapt, a.fc_bytes != 0);
@@ -1127,11 +1126,9 @@ decode_kernel(DecodeArgs a) {
       }
     }
 
-    if (LZ && a.stats) {
-      if (lane == 0) atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)listed_frame);
-      if (ft == 0)
-        atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)t * (unsigned long long)((n + 1) / 2));
-    }
+    // the stats: pairs evaluated (the transformed ones are counted per round)
+    if (LZ && a.stats && ft == 0)
+      atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)t * (unsigned long long)((n + 1) / 2));
 
     // output: x, or sign(X) when T was reached with smoothing on (Sec. III-E)
     for (int i = ft; i < a.xw_words; i += FT) xw[i] = 0u;
