@@ -640,29 +640,39 @@ decode_kernel(DecodeArgs a) {
       X2[2 * r] = X2[2 * r + 1] = (kXBias << 16) | kXBias;
       deg4[r] = dg;
       xneg |= nib << (4 * r);
-      if (j < nq && nib) atomicOr(&xw[j >> 3], nib << (4 * (j & 7)));
     }
     frame_sync<WPF>();
 
-    // s(0), u(0) and the unsatisfied count from x(0)
-    uint32_t nunsat = 0;
-    for (int i = ft; i < m; i += FT) {
-      const int e0 = tab.row_begin(i), e1 = tab.row_end(i);
-      uint32_t v = 0;
-      for (int e = e0; e < e1; ++e) {
-        const int k = tab.col_idx[e];
-        v ^= (xw[k >> 5] >> (k & 31)) & 1u;
-      }
-      if (v) {
-        atomicOr(&sw[i >> 5], 1u << (i & 31));
-        ++nunsat;
-        for (int e = e0; e < e1; ++e) {
-          const int k = tab.col_idx[e];
-          atomicAdd(&uw[k >> 2], 1u << (8 * (k & 3)));
+    // s(0), u(0) and the unsatisfied count from x(0).  s(0) is the parity of
+    // the bits with x_k = -1 (few), each toggling its checks; u(0) is gathered
+    // per bit with consecutive lanes on consecutive bits, so that the edge
+    // lists are read in near-contiguous runs.
+#pragma unroll
+    for (int r = 0; r < QPL; ++r) {
+      const int j = ft + FT * r;
+      uint32_t nib = (xneg >> (4 * r)) & 15u;
+      while (nib) {
+        const int k = 4 * j + __builtin_ctz(nib);
+        nib &= nib - 1;
+        for (int e = tab.col_begin(k), e1 = tab.col_end(k); e < e1; ++e) {
+          const int i = tab.row_idx[e];
+          atomicXor(&sw[i >> 5], 1u << (i & 31));
         }
       }
     }
+    frame_sync<WPF>();
+    uint32_t nunsat = 0;
+    for (int wd = ft; wd < a.sw_words; wd += FT) nunsat += __builtin_popcount(sw[wd]);
     if (nunsat) atomicAdd(cnt, nunsat);
+    uint8_t *ub = (uint8_t *)uw;
+    for (int k = ft; k < n; k += FT) {
+      uint32_t uk = 0;
+      for (int e = tab.col_begin(k), e1 = tab.col_end(k); e < e1; ++e) {
+        const int i = tab.row_idx[e];
+        uk += (sw[i >> 5] >> (i & 31)) & 1u;
+      }
+      ub[k] = (uint8_t)uk;
+    }
     frame_sync<WPF>();
 
     int t = 0;
