@@ -665,13 +665,29 @@ decode_kernel(DecodeArgs a) {
     for (int wd = ft; wd < a.sw_words; wd += FT) nunsat += __builtin_popcount(sw[wd]);
     if (nunsat) atomicAdd(cnt, nunsat);
     uint8_t *ub = (uint8_t *)uw;
-    for (int k = ft; k < n; k += FT) {
-      uint32_t uk = 0;
-      for (int e = tab.col_begin(k), e1 = tab.col_end(k); e < e1; ++e) {
-        const int i = tab.row_idx[e];
-        uk += (sw[i >> 5] >> (i & 31)) & 1u;
+    if (REG && (a.dv & 1) == 0 && (a.off_row & 1) == 0) {
+      // even degree: bit k's edge list is dv / 2 aligned 32-bit words
+      const uint32_t *r32 = (const uint32_t *)tab.row_idx;
+      const int dh = a.dv >> 1;
+      for (int k = ft; k < n; k += FT) {
+        uint32_t uk = 0;
+        const int w0 = (int)__umul24(k, dh);
+        for (int e = 0; e < dh; ++e) {
+          const uint32_t pr = r32[w0 + e];
+          const int i0 = (int)(pr & 0xFFFFu), i1 = (int)(pr >> 16);
+          uk += ((sw[i0 >> 5] >> (i0 & 31)) & 1u) + ((sw[i1 >> 5] >> (i1 & 31)) & 1u);
+        }
+        ub[k] = (uint8_t)uk;
       }
-      ub[k] = (uint8_t)uk;
+    } else {
+      for (int k = ft; k < n; k += FT) {
+        uint32_t uk = 0;
+        for (int e = tab.col_begin(k), e1 = tab.col_end(k); e < e1; ++e) {
+          const int i = tab.row_idx[e];
+          uk += (sw[i >> 5] >> (i & 31)) & 1u;
+        }
+        ub[k] = (uint8_t)uk;
+      }
     }
     frame_sync<WPF>();
 
