@@ -475,6 +475,8 @@ def main() -> int:
     ap.add_argument("--shape", default="", help="fix the launch shape: waves,quads,frames_per_block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-draw-stats", action="store_true",
+                    help="skip the extra decode that counts the Gaussian draws (profiling runs)")
     ap.add_argument("--mix-autotune", action="store_true", help="mix4: autotune each code first")
     ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: arrival window")
@@ -602,7 +604,7 @@ def main() -> int:
     # whose decision the radius bound fixed without a Box-Muller transform
     counted = (params.get("variant", 0) == 0 and params.get("quant_bits", 0) == 0
                and params.get("noise_reuse", 0) == 0)
-    if counted:
+    if counted and not args.no_draw_stats:
         counters = torch.zeros(2, dtype=torch.int64, device="cuda")
         ng.ngdbf_code_set_stats(dev_code.handle, counters)
         ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
