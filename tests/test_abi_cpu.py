@@ -81,6 +81,8 @@ def test_batch_and_shape_reject_bad_arguments(L):
         ng._check(L_status)
     with pytest.raises(ng.NgdbfError, match="code is NULL"):
         ng.ngdbf_code_set_shape(None, 1, 4, 8)
+    with pytest.raises(ng.NgdbfError, match="code is NULL"):
+        ng.ngdbf_code_set_stats(None, None)
     p = ng.Params().c(ng.NGDBF_Y_F32)
     bad = ng.ngdbf_job(None, None, 0, None, 0.5, p, 1, 0, None, None, None)
     with pytest.raises(ng.NgdbfError, match="job 0: code is NULL"):
