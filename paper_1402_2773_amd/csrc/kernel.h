@@ -5,12 +5,13 @@
 //   HBM: y frame-major [F][n] (float32 or int8), sigma [F], outputs
 //        out_bits [F][ceil(n/8)], out_iters [F], out_converged [F].
 //   Code tables: uint16 N(i) (CSR) and M(k) (CSC), staged into LDS once per
-//        workgroup.
+//        workgroup (read from global memory by the base kernel with four or
+//        more waves per frame).
 //   LDS per frame: syndrome bits s, per-bit counts u_k of unsatisfied checks,
-//        the unsatisfied-check count, an x / flip bit row, a toggle-event list;
-//        for the extended decoders also two reduction words and, with noise
-//        reuse, the frame's sample stream.  Per wavefront a small Box-Muller
-//        work list.
+//        the unsatisfied-check count, an x / flip bit row, a toggle row and a
+//        toggle-event list; the base kernel's flip counts; for the extended
+//        decoders also two reduction words and, with noise reuse, the frame's
+//        sample stream.  Per wavefront a small Box-Muller work list.
 //   Registers: each lane owns QPL bit quads (bits 4j .. 4j+3) and keeps their
 //        saturated y_k, smoothing counters and decisions (the extended
 //        decoders also their thresholds theta_k; the base decoder keeps a
@@ -363,7 +364,10 @@ struct Tables {
 //
 // Per frame in LDS: s (one bit per check, 1 = unsatisfied), u_k (one byte per
 // bit: number of unsatisfied checks among M(k)), the count of unsatisfied
-// checks, and an x / flip bit row.  Per wave: the Box-Muller list.
+// checks, an x / flip bit row, the round's toggle row and event list.  Per
+// wave: the Box-Muller list.  At the frame's start s(0) comes from the bits
+// with x_k = -1 toggling their checks, u(0) from a gather over each bit's
+// checks.
 //
 // Round t (Sec. III-B/C/D):
 //   stop test on the unsatisfied count;
@@ -372,8 +376,10 @@ struct Tables {
 //   Box-Muller radius settles (below) needs no transform; the others are
 //   compacted into the wave's list, transformed densely, and finished by
 //   their owners with E_k = fmaf(qs, z_k, a_k) < theta_k;
-//   each flip toggles s_i of its checks with LDS atomics, and each toggle
-//   moves u of the check's bits and the unsatisfied count by +-1.
+//   each flip xors its checks into the toggle row; the owner of each word of
+//   s applies its toggles and lists one event per toggled check; every lane
+//   then moves u of the listed checks' bits by +-1 (and the owners the
+//   unsatisfied count).
 //
 // Exactness of the bound.  With m = (a >> 8) + 1 = f 2^e, u1 >= 2^(e-24), so
 // the radius is at most sqrt(2 (24 - e) ln 2) (the computed radius exceeds it
