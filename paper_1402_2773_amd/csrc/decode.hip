@@ -15,6 +15,7 @@
 #include <cstdarg>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -142,8 +143,18 @@ using ngdbf_host::Shape;
 
 // ---------------------------------------------------------------- devices
 
+// Frame queues: every launch takes one pair of device counters (the next
+// frame to hand out, the takers that have finished) from a ring of
+// kQueueSlots; its last taker sets them back to zero, so a launch finds its
+// pair zero whether it runs directly or replayed from a captured graph.
+// Launches in flight together take different pairs; a graph must not be
+// replayed on two streams at the same time.
+constexpr int kQueueSlots = 4096;
+
 struct DeviceState {
   int cus = 0;
+  unsigned long long *queues = nullptr;  // kQueueSlots pairs, allocated with the first code
+  std::atomic<uint32_t> next_queue{0};
   std::mutex mu;                      // guards the fork/join pool below
   std::vector<hipStream_t> streams;   // library streams for batched jobs
   std::vector<hipEvent_t> events;     // one per stream, plus the fork event
@@ -166,6 +177,35 @@ DeviceState &device_state(int dev) {
 }  // namespace
 
 int ngdbf_host::device_cus(int dev) { return device_state(dev).cus; }
+
+namespace {
+
+// allocate (and zero) the device's frame queues once; not inside a capture
+int ensure_queues(int dev) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  DeviceState &st = device_state(dev);
+  if (st.queues) return NGDBF_OK;
+  const size_t bytes = (size_t)kQueueSlots * 2 * sizeof(unsigned long long);
+  unsigned long long *q = nullptr;
+  if (hipMalloc((void **)&q, bytes) != hipSuccess)
+    return fail(NGDBF_ENOMEM, "device allocation of the frame queues failed");
+  if (hipMemset(q, 0, bytes) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(q);
+    return fail(NGDBF_EDEVICE, "clearing the frame queues failed");
+  }
+  st.queues = q;  // kept until the process ends
+  return NGDBF_OK;
+}
+
+unsigned long long *take_queue(int dev) {
+  DeviceState &st = device_state(dev);
+  if (!st.queues) return nullptr;
+  const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
+  return st.queues + 2 * (size_t)i;
+}
+
+}  // namespace
 
 namespace {
 
@@ -302,7 +342,8 @@ int check_shape(const ngdbf_code *c, const Shape &sh, const Layout &L) {
     return fail(NGDBF_EINVAL, "a frame of several waves is a workgroup of its own");
   if (sh.fpb < 1 || sh.block() > 1024)
     return fail(NGDBF_EINVAL, "workgroup of %d threads", sh.block());
-  if (lds_bytes(c, sh, L) > 160 * 1024)
+  // (the kernel adds a few bytes of static LDS: the workgroup's frame index)
+  if (lds_bytes(c, sh, L) > 160 * 1024 - 256)
     return fail(NGDBF_EUNSUPPORTED, "shape needs %zu B of LDS", lds_bytes(c, sh, L));
   return NGDBF_OK;
 }
@@ -462,6 +503,8 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.fc_off = plan.fc_off;
   a.fc_bytes = p->t_max <= 255 ? 1 : 0;
   a.stats = code->stats;
+  a.queue = take_queue(dev);
+  if (!a.queue) return fail(NGDBF_EDEVICE, "no frame queues on device %d", dev);
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;
@@ -621,6 +664,10 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   c->max_col_deg = maxc;
   c->shape[0] = c->shape[1] = c->shape[2] = 0;
   const size_t bytes = (size_t)words * 4;
+  if (int qrc = ensure_queues(dev)) {
+    free(c);
+    return qrc;
+  }
   if (hipMalloc((void **)&c->d_tables, bytes) != hipSuccess) {
     free(c);
     return fail(NGDBF_ENOMEM, "device allocation of %zu bytes failed", bytes);

@@ -125,6 +125,9 @@ struct DecodeArgs {
   int32_t fc_off;
   int32_t fc_bytes;     // 1: one 8-bit count per bit (T <= 255), 0: 16-bit counts
   uint64_t *stats;      // base kernel: [pairs evaluated, pairs transformed], or null
+  // this launch's frame queue: [next frame to hand out, finished takers],
+  // zero at the start; the last taker to finish sets both back to zero
+  unsigned long long *queue;
 };
 
 template <int YFMT>
@@ -360,7 +363,8 @@ struct Tables {
 // Decode kernel.  WPF wavefronts cooperate on one frame; each lane owns QPL
 // bit quads j = ft + 64*WPF*r (ft = lane index within the frame).  With
 // WPF == 1 a workgroup holds several independent frames, one per wave, and
-// the round loop has no workgroup barrier.
+// the round loop has no workgroup barrier.  The grid is persistent; frames
+// come from a per-launch queue (an atomic counter).
 //
 // Per frame in LDS: s (one bit per check, 1 = unsatisfied), u_k (one byte per
 // bit: number of unsatisfied checks among M(k)), the count of unsatisfied
@@ -509,9 +513,24 @@ decode_kernel(DecodeArgs a) {
   int16_t *qstream = (int16_t *)(slot + a.stream_off);
   __syncthreads();
 
-  const int64_t slots_total = (int64_t)gridDim.x * a.frames_per_block;
-  for (int64_t f = (int64_t)blockIdx.x * a.frames_per_block + fslot; f < a.n_frames;
-       f += slots_total) {
+  // Frames are handed out one at a time from the launch's queue (a wave, or
+  // the workgroup when several waves share a frame, takes the next index), so
+  // that the workgroups finish together however the iteration counts fall.
+  __shared__ unsigned long long taken;
+  for (;;) {
+    int64_t f;
+    if (WPF == 1) {
+      unsigned long long g = 0;
+      if (lane == 0) g = atomicAdd(&a.queue[0], 1ull);
+      f = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g >> 32)) << 32) |
+                    (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)g));
+    } else {
+      if (tid == 0) taken = atomicAdd(&a.queue[0], 1ull);
+      __syncthreads();
+      f = (int64_t)taken;
+      __syncthreads();
+    }
+    if (f >= a.n_frames) break;
     int64_t fs = f;            // data slot of the frame
     uint64_t frame = a.frame_base + (uint64_t)f;
     uint32_t key0 = a.key0, key1 = a.key1;
@@ -1188,6 +1207,16 @@ decode_kernel(DecodeArgs a) {
       if (a.out_conv) a.out_conv[fs] = (uint8_t)converged;
     }
     frame_sync<WPF>();  // the slot is cleared for the next frame
+  }
+  // every taker has taken its last index; the last one to get here empties
+  // the queue for the next launch (the others' increments have returned)
+  if (WPF == 1 ? lane == 0 : tid == 0) {
+    const unsigned long long takers =
+        WPF == 1 ? (unsigned long long)gridDim.x * (blockDim.x / kWave) : (unsigned long long)gridDim.x;
+    if (atomicAdd(&a.queue[1], 1ull) == takers - 1) {
+      atomicExch(&a.queue[0], 0ull);
+      atomicExch(&a.queue[1], 0ull);
+    }
   }
 }
 
