@@ -235,6 +235,30 @@ def test_base_kernel_every_shape(torch_dev, shape, t_max):
     assert_same(g, r, trace=True)
 
 
+def test_frame_queue_reuse(torch_dev):
+    """Frames come from a per-launch queue taken from a ring of 4096 and reset
+    by the launch's last taker: 4200 launches in a row (every queue used more
+    than once, the first ones again) give the same decode each time."""
+    torch = torch_dev
+    c, dc = dev_code("C96")
+    sig = np.float32(channel.sigma_from_ebn0(3.0, c.rate))
+    y = channel.bpsk_awgn(40, c.n, sig, seed=70)
+    p = ng.Params(**P_C1.__dict__)
+    y_dev = torch.from_numpy(y).cuda()
+    ref = ng.decode(dc, y_dev, float(sig), p, 71)
+    out = ng.decode(dc, y_dev, float(sig), p, 71)
+    say("queue reuse: 4200 launches")
+    for i in range(4200):
+        ng.decode(dc, y_dev, float(sig), p, 71, out=out)
+        if i % 700 == 699:
+            torch.cuda.synchronize()
+            assert torch.equal(out.iters, ref.iters) and torch.equal(out.bits, ref.bits), f"launch {i}"
+    torch.cuda.synchronize()
+    assert torch.equal(out.iters, ref.iters) and torch.equal(out.bits, ref.bits)
+    r = oracle.decode(c, y, sig, P_C1, 71)
+    assert (ref.iters.cpu().numpy() == r.iters).all()
+
+
 def test_settle_statistics(torch_dev):
     """The settle-test counters: every round of every frame evaluates ceil(n/2)
     pairs, a minority of them is transformed, and the decode is unchanged."""
