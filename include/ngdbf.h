@@ -102,8 +102,8 @@ typedef struct {
  *   out      : receives the handle.
  * The arrays are copied; the column supports M(k) are built here.  The first
  * code on a device also allocates and clears that device's frame queues
- * (4096 pairs of counters, 64 KB, kept until the process ends; every decode
- * launch takes one pair, see ngdbf_decode), so create codes outside a stream
+ * (1024 queues of 9 cache-line-padded counters, 1.2 MB, kept until the
+ * process ends; every decode launch takes one queue, see ngdbf_decode), so create codes outside a stream
  * capture.
  * Errors: NGDBF_EINVAL (bad sizes, indices, empty row or column),
  * NGDBF_EUNSUPPORTED (a column degree above 15, an irregular code with more
@@ -137,10 +137,11 @@ int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  *   out_converged : dev uint8 [n_frames] (may be NULL): 1 if the stop test
  *                (every s_i = +1) ended decoding, 0 if T was reached.
  *   stream     : hipStream_t.
- * The launch's waves take frames one at a time from a queue (a pair of device
- * counters from the device's ring of 4096, reset by the launch itself when it
- * ends), so at most 4096 launches may be in flight at once, and a captured
- * graph must not be replayed on two streams at the same time.
+ * The launch's waves take frames as they need them from a queue (8 device
+ * counters of frame runs plus a count of finished waves, from the device's
+ * ring of 1024 queues, reset by the launch itself when it ends), so at most
+ * 1024 launches may be in flight at once, and a captured graph must not be
+ * replayed on two streams at the same time.
  * Errors: NGDBF_EINVAL (NULL pointers with n_frames > 0, parameters out of
  * range), NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
  */

@@ -143,17 +143,17 @@ using ngdbf_host::Shape;
 
 // ---------------------------------------------------------------- devices
 
-// Frame queues: every launch takes one pair of device counters (the next
-// frame to hand out, the takers that have finished) from a ring of
-// kQueueSlots; its last taker sets them back to zero, so a launch finds its
-// pair zero whether it runs directly or replayed from a captured graph.
-// Launches in flight together take different pairs; a graph must not be
-// replayed on two streams at the same time.
-constexpr int kQueueSlots = 4096;
+// Frame queues: every launch takes one queue (ngdbf::kQueueWords counters:
+// the runs handed out per queue lane, the takers that have finished) from a
+// ring of kQueueSlots; its last taker sets them back to zero, so a launch
+// finds its queue zero whether it runs directly or replayed from a captured
+// graph.  Launches in flight together take different queues; a graph must not
+// be replayed on two streams at the same time.
+constexpr int kQueueSlots = 1024;
 
 struct DeviceState {
   int cus = 0;
-  unsigned long long *queues = nullptr;  // kQueueSlots pairs, allocated with the first code
+  unsigned long long *queues = nullptr;  // kQueueSlots queues, allocated with the first code
   std::atomic<uint32_t> next_queue{0};
   std::mutex mu;                      // guards the fork/join pool below
   std::vector<hipStream_t> streams;   // library streams for batched jobs
@@ -186,7 +186,7 @@ int ensure_queues(int dev) {
   std::lock_guard<std::mutex> g(mu);
   DeviceState &st = device_state(dev);
   if (st.queues) return NGDBF_OK;
-  const size_t bytes = (size_t)kQueueSlots * 2 * sizeof(unsigned long long);
+  const size_t bytes = (size_t)kQueueSlots * ngdbf::kQueueWords * sizeof(unsigned long long);
   unsigned long long *q = nullptr;
   if (hipMalloc((void **)&q, bytes) != hipSuccess)
     return fail(NGDBF_ENOMEM, "device allocation of the frame queues failed");
@@ -202,7 +202,7 @@ unsigned long long *take_queue(int dev) {
   DeviceState &st = device_state(dev);
   if (!st.queues) return nullptr;
   const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
-  return st.queues + 2 * (size_t)i;
+  return st.queues + (size_t)ngdbf::kQueueWords * i;
 }
 
 }  // namespace

@@ -43,7 +43,12 @@ int launch(const ngdbf::DecodeArgs &a, const Shape &sh, size_t lds_bytes, int de
   const int64_t blocks_needed = (a.n_frames + sh.fpb - 1) / sh.fpb;
   // persistent grid: the resident capacity, or fewer blocks for small batches
   const int64_t grid = std::min<int64_t>((int64_t)per_cu * cus, blocks_needed);
-  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.block()), lds_bytes, s, a);
+  // frames per queue update: 1, or about 1/256 of a taker's share for very
+  // large batches (at most 16)
+  ngdbf::DecodeArgs args = a;
+  const int64_t takers = grid * (WPF == 1 ? sh.fpb : 1);
+  args.queue_chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(16, a.n_frames / (takers * 256)));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(sh.block()), lds_bytes, s, args);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NGDBF_EDEVICE, "launch failed: %s", hipGetErrorString(e));
   return NGDBF_OK;

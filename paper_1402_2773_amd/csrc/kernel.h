@@ -125,10 +125,20 @@ struct DecodeArgs {
   int32_t fc_off;
   int32_t fc_bytes;     // 1: one 8-bit count per bit (T <= 255), 0: 16-bit counts
   uint64_t *stats;      // base kernel: [pairs evaluated, pairs transformed], or null
-  // this launch's frame queue: [next frame to hand out, finished takers],
-  // zero at the start; the last taker to finish sets both back to zero
+  // this launch's frame queue: kQueueLanes counters of handed-out runs (one
+  // 128-byte line each) and the count of finished takers, zero at the start;
+  // the last taker to finish sets them back to zero
   unsigned long long *queue;
+  int32_t queue_chunk;  // consecutive frames per run (>= 1)
 };
+
+// A frame queue's counters: taker t draws from counter t % kQueueLanes, whose
+// runs cover frames c + kQueueLanes * (chunk * i + 0 .. chunk - 1), so that no
+// single counter carries every update.  Words between counters pad them to
+// separate cache lines.
+constexpr int kQueueLanes = 8;
+constexpr int kQueueStride = 16;  // uint64 words per counter (128 bytes)
+constexpr int kQueueWords = (kQueueLanes + 1) * kQueueStride;
 
 template <int YFMT>
 __device__ __forceinline__ float load_sample(const void *y, int64_t idx) {
@@ -513,24 +523,50 @@ decode_kernel(DecodeArgs a) {
   int16_t *qstream = (int16_t *)(slot + a.stream_off);
   __syncthreads();
 
-  // Frames are handed out one at a time from the launch's queue (a wave, or
-  // the workgroup when several waves share a frame, takes the next index), so
-  // that the workgroups finish together however the iteration counts fall.
+  // Frames are handed out from the launch's queue as they are needed, so that
+  // the workgroups finish together however the iteration counts fall.  A
+  // taker (a wave, or the workgroup when several waves share a frame) takes
+  // runs of queue_chunk frames from counter t % kQueueLanes (frame
+  // c + kQueueLanes * i is the i-th frame of counter c); once that counter is
+  // spent it moves on to the next, until all of them are.
   __shared__ unsigned long long taken;
+  // (the wave index is uniform in the wave; readfirstlane lets the compiler
+  // keep the counter index, and the frame index with it, in scalar registers)
+  const int taker = __builtin_amdgcn_readfirstlane(
+      WPF == 1 ? (int)blockIdx.x * (int)(blockDim.x / kWave) + wave : (int)blockIdx.x);
+  int qc = taker % kQueueLanes, spent = 0;
+  int64_t next = 0, end = 0;  // the taker's current run, in its counter's numbering
   for (;;) {
-    int64_t f;
-    if (WPF == 1) {
-      unsigned long long g = 0;
-      if (lane == 0) g = atomicAdd(&a.queue[0], 1ull);
-      f = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g >> 32)) << 32) |
-                    (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)g));
-    } else {
-      if (tid == 0) taken = atomicAdd(&a.queue[0], 1ull);
-      __syncthreads();
-      f = (int64_t)taken;
-      __syncthreads();
+    int64_t f = -1;  // the taker's next frame; stays -1 once every counter is spent
+    while (spent < kQueueLanes) {
+      if (next < end) {
+        const int64_t c = (int64_t)qc + (int64_t)kQueueLanes * next++;
+        if (c < a.n_frames) {
+          f = c;
+          break;
+        }
+        // this counter is spent: go on to the next one
+        ++spent;
+        qc = qc + 1 == kQueueLanes ? 0 : qc + 1;
+        next = end = 0;
+      } else {
+        const unsigned long long chunk = (unsigned long long)a.queue_chunk;
+        unsigned long long *qctr = a.queue + qc * kQueueStride;
+        unsigned long long g = 0;
+        if (WPF == 1) {
+          if (lane == 0) g = atomicAdd(qctr, chunk);
+        } else {
+          if (tid == 0) taken = atomicAdd(qctr, chunk);
+          __syncthreads();
+          g = taken;
+          __syncthreads();
+        }
+        next = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(g >> 32)) << 32) |
+                         (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)g));
+        end = next + (int64_t)chunk;
+      }
     }
-    if (f >= a.n_frames) break;
+    if (f < 0) break;
     int64_t fs = f;            // data slot of the frame
     uint64_t frame = a.frame_base + (uint64_t)f;
     uint32_t key0 = a.key0, key1 = a.key1;
@@ -1213,9 +1249,9 @@ decode_kernel(DecodeArgs a) {
   if (WPF == 1 ? lane == 0 : tid == 0) {
     const unsigned long long takers =
         WPF == 1 ? (unsigned long long)gridDim.x * (blockDim.x / kWave) : (unsigned long long)gridDim.x;
-    if (atomicAdd(&a.queue[1], 1ull) == takers - 1) {
-      atomicExch(&a.queue[0], 0ull);
-      atomicExch(&a.queue[1], 0ull);
+    if (atomicAdd(&a.queue[kQueueLanes * kQueueStride], 1ull) == takers - 1) {
+      for (int c = 0; c < kQueueLanes; ++c) atomicExch(&a.queue[c * kQueueStride], 0ull);
+      atomicExch(&a.queue[kQueueLanes * kQueueStride], 0ull);
     }
   }
 }
