@@ -236,7 +236,7 @@ def test_base_kernel_every_shape(torch_dev, shape, t_max):
 
 
 def test_frame_queue_reuse(torch_dev):
-    """Frames come from a per-launch queue taken from a ring of 4096 and reset
+    """Frames come from a per-launch queue taken from a ring of 1024 and reset
     by the launch's last taker: 4200 launches in a row (every queue used more
     than once, the first ones again) give the same decode each time."""
     torch = torch_dev
