@@ -489,8 +489,8 @@ def main() -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build decodes on a single MI355X "
-              "(frames shard trivially across GPUs, but no multi-GPU run is part of it). "
+        print("bench.py measures one GPU only: the decoder runs on a single MI355X "
+              "(frames shard trivially across GPUs, but there is no multi-GPU path). "
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 

@@ -1,4 +1,4 @@
-"""Shared fixtures.  GPU tests are marked ``gpu`` and run only on a GPU machine."""
+"""Shared fixtures.  GPU tests are marked ``gpu`` and need a HIP device."""
 import os
 import sys
 
