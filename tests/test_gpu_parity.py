@@ -283,6 +283,49 @@ def test_settle_statistics(torch_dev):
     assert counters.cpu().tolist() == [evaluated, transformed]
 
 
+def test_every_frame_once_mixed_lengths(torch_dev):
+    """2^18 frames of very different lengths (Eb/N0 drawn per frame from 1.5
+    to 6 dB): the queue's takers drain their own counter and then the
+    others'.  Every frame is decoded exactly once (outputs start at a
+    sentinel; the settle counters equal the rounds summed over frames), and
+    sampled frames equal the oracle's."""
+    torch = torch_dev
+    c, dc = dev_code("C1008")
+    F = 1 << 18
+    s = channel.frame_sigmas(F, 1.5, 6.0, c.rate, seed=72)
+    s_dev = torch.from_numpy(s).cuda()
+    y = channel.bpsk_awgn_device(F, c.n, s_dev, seed=73)
+    p = p_heur(3.5)
+    gp = ng.Params(**p.__dict__)
+    say("every frame once: 2^18 frames, 1.5 .. 6 dB")
+    out = ng.decode(dc, y, s_dev, gp, 74)
+    torch.cuda.synchronize()
+    first = out.iters.clone()
+    out.iters.fill_(-1)
+    out.converged.fill_(2)
+    out.bits.fill_(0xA5)
+    counters = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ng.ngdbf_code_set_stats(dc.handle, counters)
+    try:
+        ng.decode(dc, y, s_dev, gp, 74, out=out)
+        torch.cuda.synchronize()
+    finally:
+        ng.ngdbf_code_set_stats(dc.handle, None)
+    iters = out.iters.cpu().numpy()
+    assert (iters >= 0).all() and (iters <= p.t_max).all(), "a frame was not decoded"
+    assert (out.converged.cpu().numpy() <= 1).all()
+    assert torch.equal(out.iters, first)
+    evaluated = int(counters[0].item())
+    assert evaluated == int(iters.astype(np.int64).sum()) * ((c.n + 1) // 2), "a frame was decoded twice"
+    assert iters.min() < 20 and iters.max() == p.t_max
+    for start in (0, F // 2 + 3, F - 32):
+        yh = y[start:start + 32].cpu().numpy()
+        r = oracle.decode(c, yh, s[start:start + 32], p, 74, frame_base=start, threads=8)
+        g = (out.bits[start:start + 32].cpu().numpy(), iters[start:start + 32],
+             out.converged[start:start + 32].cpu().numpy(), None)
+        assert_same(g, r)
+
+
 @pytest.mark.parametrize("t_max", [5000, 9000])
 def test_long_adaptive_schedule(torch_dev, t_max):
     """Adaptive thresholds over thousands of rounds: the base kernel's table of
