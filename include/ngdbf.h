@@ -102,7 +102,7 @@ typedef struct {
  *   out      : receives the handle.
  * The arrays are copied; the column supports M(k) are built here.  The first
  * code on a device also allocates and clears that device's frame queues
- * (1024 queues of 9 cache-line-padded counters, 1.2 MB, kept until the
+ * (2 x 1024 queues of 9 cache-line-padded counters, 2.4 MB, kept until the
  * process ends; every decode launch takes one queue, see ngdbf_decode), so create codes outside a stream
  * capture.
  * Errors: NGDBF_EINVAL (bad sizes, indices, empty row or column),
@@ -138,10 +138,15 @@ int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  *                (every s_i = +1) ended decoding, 0 if T was reached.
  *   stream     : hipStream_t.
  * The launch's waves take frames as they need them from a queue (8 device
- * counters of frame runs plus a count of finished waves, from the device's
- * ring of 1024 queues, reset by the launch itself when it ends), so at most
- * 1024 launches may be in flight at once, and a captured graph must not be
- * replayed on two streams at the same time.
+ * counters of frame runs plus a count of finished waves, reset by the launch
+ * itself when it ends).  Direct launches take queues from one ring of 1024,
+ * launches recorded under stream capture from another ring of 1024, so a
+ * graph's launches never share a queue with direct launches.  At most 1024
+ * direct launches may be in flight at once; at most 1024 recorded launches
+ * may belong to graphs replayed at the same time; a captured graph must not
+ * be replayed on two streams at the same time.  With trace rows, the rows
+ * are cleared by a kernel on `stream` before the decode (no memset node
+ * under capture).
  * Errors: NGDBF_EINVAL (NULL pointers with n_frames > 0, parameters out of
  * range), NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
  */

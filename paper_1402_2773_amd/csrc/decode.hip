@@ -29,6 +29,13 @@ namespace ngdbf {
 
 // ---------------------------------------------------------------- probes
 
+// zero n bytes (the trace rows; a kernel rather than a memset node, so that
+// a captured graph clears them on every replay)
+__global__ void clear_bytes_kernel(uint8_t *p, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
 __global__ void probe_radius_kernel(uint32_t start, uint32_t count, float *out) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < count) out[j] = bm_radius(start + j);
@@ -144,17 +151,23 @@ using ngdbf_host::Shape;
 // ---------------------------------------------------------------- devices
 
 // Frame queues: every launch takes one queue (ngdbf::kQueueWords counters:
-// the runs handed out per queue lane, the takers that have finished) from a
-// ring of kQueueSlots; its last taker sets them back to zero, so a launch
-// finds its queue zero whether it runs directly or replayed from a captured
-// graph.  Launches in flight together take different queues; a graph must not
-// be replayed on two streams at the same time.
+// the runs handed out per queue lane, the takers that have finished); its
+// last taker sets them back to zero, so a launch finds its queue zero whether
+// it runs directly or replayed from a captured graph.  Direct launches take
+// queues from a ring of kQueueSlots, launches recorded into a graph from a
+// ring of kCapturedSlots of their own, so that a graph's queues are never
+// those of direct launches running beside its replays.  Launches in flight
+// together take different queues; a graph must not be replayed on two
+// streams at the same time.
 constexpr int kQueueSlots = 1024;
+constexpr int kCapturedSlots = 1024;
 
 struct DeviceState {
   int cus = 0;
-  unsigned long long *queues = nullptr;  // kQueueSlots queues, allocated with the first code
-  std::atomic<uint32_t> next_queue{0};
+  // kQueueSlots + kCapturedSlots queues, allocated with the first code
+  unsigned long long *queues = nullptr;
+  std::atomic<uint32_t> next_queue{0};     // direct launches
+  std::atomic<uint32_t> next_captured{0};  // launches recorded under stream capture
   std::mutex mu;                      // guards the fork/join pool below
   std::vector<hipStream_t> streams;   // library streams for batched jobs
   std::vector<hipEvent_t> events;     // one per stream, plus the fork event
@@ -186,7 +199,8 @@ int ensure_queues(int dev) {
   std::lock_guard<std::mutex> g(mu);
   DeviceState &st = device_state(dev);
   if (st.queues) return NGDBF_OK;
-  const size_t bytes = (size_t)kQueueSlots * ngdbf::kQueueWords * sizeof(unsigned long long);
+  const size_t bytes =
+      (size_t)(kQueueSlots + kCapturedSlots) * ngdbf::kQueueWords * sizeof(unsigned long long);
   unsigned long long *q = nullptr;
   if (hipMalloc((void **)&q, bytes) != hipSuccess)
     return fail(NGDBF_ENOMEM, "device allocation of the frame queues failed");
@@ -198,11 +212,26 @@ int ensure_queues(int dev) {
   return NGDBF_OK;
 }
 
-unsigned long long *take_queue(int dev) {
+unsigned long long *take_queue(int dev, bool captured) {
   DeviceState &st = device_state(dev);
   if (!st.queues) return nullptr;
-  const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
+  const uint32_t i = captured ? (uint32_t)kQueueSlots + st.next_captured.fetch_add(1u) % (uint32_t)kCapturedSlots
+                              : st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
   return st.queues + (size_t)ngdbf::kQueueWords * i;
+}
+
+// Whether work queued on `s` now is recorded into a graph.  With an earlier
+// error pending nothing is asked (the caller reports that error next); an
+// error of the query itself (the legacy stream during a global capture)
+// counts as "not capturing" and is cleared.
+bool stream_capturing(hipStream_t s) {
+  if (hipPeekAtLastError() != hipSuccess) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs == hipStreamCaptureStatusActive;
 }
 
 }  // namespace
@@ -434,7 +463,7 @@ struct Prepared {
 int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
             float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
             uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
-            const Shape *force, Prepared *out, const ngdbf_segment *segments = nullptr,
+            const Shape *force, Prepared *out, bool captured, const ngdbf_segment *segments = nullptr,
             int32_t n_segments = 0, int64_t pool_frames = -1) {
   // host-side validation, parameters first (no device state is touched)
   int rc = check_params(p);
@@ -503,7 +532,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.fc_off = plan.fc_off;
   a.fc_bytes = p->t_max <= 255 ? 1 : 0;
   a.stats = code->stats;
-  a.queue = take_queue(dev);
+  a.queue = take_queue(dev, captured);
   if (!a.queue) return fail(NGDBF_EDEVICE, "no frame queues on device %d", dev);
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
@@ -566,17 +595,18 @@ int decode_common(const ngdbf_code *code, const void *y, int64_t n_frames, const
                   float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
                   uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
                   void *stream) {
+  hipStream_t s = (hipStream_t)stream;
   Prepared pr;
   int rc = prepare(code, y, n_frames, sigma, sigma_scalar, p, seed, frame_base, out_bits,
-                   out_iters, out_conv, trace, nullptr, &pr);
+                   out_iters, out_conv, trace, nullptr, &pr, stream_capturing(s));
   if (rc) return rc;
   rc = pending_error();
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
   if (trace && n_frames > 0 && p->t_max > 0) {
     const size_t tb = (size_t)n_frames * (size_t)p->t_max * (size_t)((code->n + 7) / 8);
-    if (hipMemsetAsync(trace, 0, tb, s) != hipSuccess)
-      return fail(NGDBF_EDEVICE, "trace clear failed");
+    const size_t blocks = std::min<size_t>((tb + 255) / 256, 4096);
+    hipLaunchKernelGGL(ngdbf::clear_bytes_kernel, dim3((unsigned)blocks), dim3(256), 0, s, trace, tb);
+    if (hipGetLastError() != hipSuccess) return fail(NGDBF_EDEVICE, "trace clear failed");
   }
   return enqueue(pr, s);
 }
@@ -773,7 +803,8 @@ int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool, const floa
   if (pool_frames < 0) return fail(NGDBF_EINVAL, "pool_frames < 0");
   Prepared pr;
   int rc = prepare(code, y_pool, n_frames, sigma_pool, sigma_scalar, params, 0, 0, bits_pool,
-                   iters_pool, conv_pool, nullptr, nullptr, &pr, segments, n_segments, pool_frames);
+                   iters_pool, conv_pool, nullptr, nullptr, &pr, stream_capturing((hipStream_t)stream),
+                   segments, n_segments, pool_frames);
   if (rc) return rc;
   rc = pending_error();
   if (rc) return rc;
@@ -849,7 +880,7 @@ int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const floa
       if (check_shape(code, cand, layout_of(code, params, false)) != NGDBF_OK) continue;
       Prepared pr;
       rc = prepare(code, y, n_frames, sigma, sigma_scalar, params, seed, 0, bits, iters, nullptr,
-                   nullptr, &cand, &pr);
+                   nullptr, &cand, &pr, false);
       if (rc) break;
       rc = enqueue(pr, s);  // warm-up
       if (rc == NGDBF_EUNSUPPORTED) {  // rejected before launch (occupancy, LDS)
@@ -896,11 +927,13 @@ int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const floa
 int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(NGDBF_EINVAL, "bad job array");
   std::vector<Prepared> prs((size_t)n_jobs);
+  // the library streams join a capture of `stream` through the fork event
+  const bool captured = n_jobs > 0 && stream_capturing((hipStream_t)stream);
   for (int i = 0; i < n_jobs; ++i) {
     const ngdbf_job &j = jobs[i];
     const int rc = prepare(j.code, j.y, j.n_frames, j.sigma, j.sigma_scalar, &j.params, j.seed,
                            j.frame_base, j.out_bits, j.out_iters, j.out_converged, nullptr,
-                           nullptr, &prs[i]);
+                           nullptr, &prs[i], captured);
     if (rc) {
       char msg[512];
       snprintf(msg, sizeof msg, "%s", g_err);

@@ -259,6 +259,53 @@ def test_frame_queue_reuse(torch_dev):
     assert (ref.iters.cpu().numpy() == r.iters).all()
 
 
+def test_graph_replays_beside_direct_launches(torch_dev):
+    """Launches recorded into a graph take their queues from a ring of their
+    own: replays of a captured decode (and a captured traced decode, whose
+    trace rows are cleared by a kernel on every replay) interleaved with 1100
+    direct launches on another stream, more than the direct ring holds,
+    reproduce the eager results every time."""
+    torch = torch_dev
+    c, dc = dev_code("C1008")
+    sig = np.float32(channel.sigma_from_ebn0(3.5, c.rate))
+    y = channel.bpsk_awgn(4096, c.n, sig, seed=75)
+    gp = ng.Params(**p_heur(3.5).__dict__)
+    y_dev = torch.from_numpy(y).cuda()
+    ref = ng.decode(dc, y_dev, float(sig), gp, 76)
+    ref_tr = ng.decode(dc, y_dev[:16], float(sig), gp, 78, trace=True)
+    out_g = ng.decode(dc, y_dev, float(sig), gp, 76)
+    out_tr = ng.decode(dc, y_dev[:16], float(sig), gp, 78, trace=True)
+    y2 = y_dev[:64].contiguous()
+    ref2 = ng.decode(dc, y2, float(sig), gp, 77)
+    out2 = ng.decode(dc, y2, float(sig), gp, 77)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(g, stream=cs):
+            ng.decode(dc, y_dev, float(sig), gp, 76, out=out_g, stream=cs)
+            ng.decode(dc, y_dev[:16], float(sig), gp, 78, trace=True, out=out_tr, stream=cs)
+    torch.cuda.synchronize()
+    other = torch.cuda.Stream()
+    say("graph replays beside 1100 direct launches")
+    for i in range(1100):
+        ng.decode(dc, y2, float(sig), gp, 77, out=out2, stream=other)
+        if i % 100 == 50:
+            out_g.iters.fill_(-1)
+            out_tr.trace.fill_(0xFF)
+            cs.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(cs):
+                g.replay()
+        if i % 100 == 99:
+            torch.cuda.synchronize()
+            assert torch.equal(out_g.iters, ref.iters) and torch.equal(out_g.bits, ref.bits), f"replay {i}"
+            assert torch.equal(out_tr.trace, ref_tr.trace) and torch.equal(out_tr.iters, ref_tr.iters)
+            assert torch.equal(out2.iters, ref2.iters) and torch.equal(out2.bits, ref2.bits), f"direct {i}"
+    torch.cuda.synchronize()
+    del g
+
+
 def test_settle_statistics(torch_dev):
     """The settle-test counters: every round of every frame evaluates ceil(n/2)
     pairs, a minority of them is transformed, and the decode is unchanged."""
