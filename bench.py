@@ -32,9 +32,9 @@ PEAK_HBM_GBS = 8000.0
 
 def _heur(ebn0: float):
     """Adaptive-threshold SM-NGDBF parameters of Sec. IV-A: theta -0.9,
-    eta 0.95, lambda 0.99 below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 above;
-    w = 0.75, Y_max = 2.5, smoothing over the last 64 rounds, T = 300."""
-    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.5 else 0.90
+    eta 0.95, lambda 0.99 below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 from
+    4.25 dB; w = 0.75, Y_max = 2.5, smoothing over the last 64 rounds, T = 300."""
+    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.25 else 0.90
     return dict(w=0.75, theta=-0.9, lam=lam, eta=0.95, ymax=2.5, t_max=300, smooth_window=64)
 
 

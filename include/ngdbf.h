@@ -46,7 +46,9 @@ typedef enum {
     NGDBF_EINVAL = -1,       /* invalid argument                              */
     NGDBF_ENOMEM = -2,       /* device or host allocation failed             */
     NGDBF_EDEVICE = -3,      /* HIP runtime error                             */
-    NGDBF_EUNSUPPORTED = -4  /* valid, but outside what the kernels support  */
+    NGDBF_EUNSUPPORTED = -4, /* valid, but outside what the kernels support  */
+    NGDBF_EBUSY = -5         /* every frame queue of the device is held by a
+                                launch still in flight (see ngdbf_decode)     */
 } ngdbf_status;
 
 /* Opaque handle: a parity-check matrix H resident on one device. */
@@ -96,8 +98,10 @@ typedef struct {
  * ngdbf_create_code -- upload H (Sec. III-A: N(i) row supports, M(k) column
  * supports) to the current device.
  *   n, m     : bits (columns) and checks (rows), 1 <= m < n <= 65535.
- *   row_ptr  : host, int32 [m+1], row_ptr[0] = 0, non-decreasing.
- *   col_idx  : host, int32 [row_ptr[m]], N(i) = col_idx[row_ptr[i] ..
+ *   nnz      : edges of H (ones in the matrix), = row_ptr[m], at most 2^24.
+ *   row_ptr  : host, int32 [m+1], row_ptr[0] = 0, strictly increasing (no
+ *              empty row).
+ *   col_idx  : host, int32 [nnz], N(i) = col_idx[row_ptr[i] ..
  *              row_ptr[i+1]-1], each in [0, n), no repeats within a row.
  *   out      : receives the handle.
  * The arrays are copied; the column supports M(k) are built here.  The first
@@ -110,16 +114,17 @@ typedef struct {
  * than 65535 edges), NGDBF_ENOMEM, NGDBF_EDEVICE.  A code whose tables do not
  * fit the LDS of any launch shape is refused by the decode calls.
  */
-int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr,
-                      const int32_t *col_idx, ngdbf_code **out);
+ngdbf_status ngdbf_create_code(int32_t n, int32_t m, int64_t nnz,
+                               const int32_t *row_ptr, const int32_t *col_idx,
+                               ngdbf_code **out);
 
 /* Release a handle and its device tables (NULL is accepted). The caller must
  * ensure no decode using it is still running. */
-int ngdbf_destroy_code(ngdbf_code *code);
+ngdbf_status ngdbf_destroy_code(ngdbf_code *code);
 
 /* Sizes of a handle: n, m, nnz (any output pointer may be NULL). */
-int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
-                    int32_t *nnz);
+ngdbf_status ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
+                             int32_t *nnz);
 
 /*
  * ngdbf_decode -- decode n_frames received frames (Sec. III, all steps).
@@ -127,7 +132,10 @@ int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  *   n_frames   : >= 0 (0 queues nothing).
  *   sigma      : dev float32 [n_frames] channel std per frame, or NULL to use
  *                sigma_scalar for every frame; the perturbation std is
- *                fl(eta * sigma) (Sec. III-C).  sigma must be >= 0 and finite.
+ *                fl(eta * sigma) (Sec. III-C).  sigma_scalar must be >= 0 and
+ *                finite; per-frame values are used as given (a negative value
+ *                draws fl(eta * sigma) z_k exactly as the definition says, and
+ *                the exact noise skip bounds its magnitude).
  *   params     : host.
  *   seed       : Philox key.  frame_base: global index of frame 0 (noise
  *                counter), so a split or resumed run reproduces per-frame results.
@@ -150,7 +158,7 @@ int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  * Errors: NGDBF_EINVAL (NULL pointers with n_frames > 0, parameters out of
  * range), NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
  */
-int ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames,
+ngdbf_status ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames,
                  const float *sigma, float sigma_scalar,
                  const ngdbf_params *params, uint64_t seed, uint64_t frame_base,
                  uint8_t *out_bits, int32_t *out_iters, uint8_t *out_converged,
@@ -164,7 +172,7 @@ int ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames,
  *                run are written as zero.
  * Other arguments and errors as ngdbf_decode.  Slower; for verification.
  */
-int ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames,
+ngdbf_status ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames,
                        const float *sigma, float sigma_scalar,
                        const ngdbf_params *params, uint64_t seed,
                        uint64_t frame_base, uint8_t *out_bits,
@@ -183,7 +191,7 @@ int ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames,
  *   out0/out1: dev float32 (out1 only for kind 1).  count >= 0.
  * Errors: NGDBF_EINVAL (kind or range), NGDBF_EDEVICE.
  */
-int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
+ngdbf_status ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
                       uint64_t seed, uint64_t frame, uint32_t iter,
                       float *out0, float *out1, void *stream);
 
@@ -206,9 +214,9 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
  * one wave per frame whenever the code fits in 1024 bits.
  * Not thread-safe against concurrent decodes of the same code.
  */
-int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,
+ngdbf_status ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,
                          int32_t quads_per_lane, int32_t frames_per_block);
-int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
+ngdbf_status ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
                          int32_t shape[3]);
 
 /*
@@ -226,7 +234,7 @@ int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params,
  * thread-safe against concurrent decodes of the same code.
  * Errors: NGDBF_EINVAL (code is NULL).
  */
-int ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters);
+ngdbf_status ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters);
 
 /*
  * ngdbf_autotune -- time every built launch shape that fits the code on the
@@ -239,7 +247,7 @@ int ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters);
  *   elapsed_ms : host float (may be NULL), its time on the sample.
  * Synchronises the stream.  Errors as ngdbf_decode, NGDBF_ENOMEM.
  */
-int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames,
+ngdbf_status ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames,
                    const float *sigma, float sigma_scalar,
                    const ngdbf_params *params, uint64_t seed, int32_t best[3],
                    float *elapsed_ms, void *stream);
@@ -271,7 +279,7 @@ typedef struct {
  * jobs: host array [n_jobs]; all codes on the current device.
  * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0), NGDBF_EDEVICE.
  */
-int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
+ngdbf_status ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
 
 /*
  * Segmented decoding: frames scattered over slot ranges of resident pools.
@@ -300,7 +308,7 @@ typedef struct {
  * a frame whose slot falls outside is skipped (nothing is read or written).
  * Errors as ngdbf_decode.
  */
-int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool,
+ngdbf_status ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool,
                           const float *sigma_pool, float sigma_scalar,
                           int64_t pool_frames, const ngdbf_params *params,
                           const ngdbf_segment *segments, int32_t n_segments,
@@ -335,18 +343,18 @@ typedef struct ngdbf_server ngdbf_server;
  *                                wait and join the next launch of their code.
  *   out                        : receives the handle (NULL on failure).
  */
-int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes,
+ngdbf_status ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes,
                         const ngdbf_params *params, const int64_t *pool_frames,
                         int32_t n_streams, int32_t max_requests_per_launch,
                         int32_t launches_per_stream, ngdbf_server **out);
 /* Waits for launches in flight, then frees everything the server owns. */
-int ngdbf_server_destroy(ngdbf_server *server);
+ngdbf_status ngdbf_server_destroy(ngdbf_server *server);
 /*
  * ngdbf_server_pools -- device addresses of code `code_index`'s pools (any
  * output pointer may be NULL).  The client writes y and sigma of a request's
  * slots before committing it and reads its outputs once poll has reported it.
  */
-int ngdbf_server_pools(ngdbf_server *server, int32_t code_index, float **y,
+ngdbf_status ngdbf_server_pools(ngdbf_server *server, int32_t code_index, float **y,
                        float **sigma, uint8_t **bits, int32_t **iters,
                        uint8_t **converged);
 /*
@@ -357,7 +365,7 @@ int ngdbf_server_pools(ngdbf_server *server, int32_t code_index, float **y,
  * admitted prefix of *n_admitted requests.  A request larger than its pool is
  * NGDBF_EINVAL.
  */
-int ngdbf_server_admit(ngdbf_server *server, int32_t n_requests,
+ngdbf_status ngdbf_server_admit(ngdbf_server *server, int32_t n_requests,
                        const int32_t *code_index, const int64_t *n_frames,
                        const uint64_t *seed, const uint64_t *frame_base,
                        uint64_t *tickets, int64_t *first_slots,
@@ -366,7 +374,7 @@ int ngdbf_server_admit(ngdbf_server *server, int32_t n_requests,
  * ngdbf_server_commit -- the admitted requests' inputs are complete once the
  * work queued so far on `stream` has run; their launch waits for it.
  */
-int ngdbf_server_commit(ngdbf_server *server, int32_t n, const uint64_t *tickets,
+ngdbf_status ngdbf_server_commit(ngdbf_server *server, int32_t n, const uint64_t *tickets,
                         void *stream);
 /*
  * ngdbf_server_pump -- launch committed requests while a stream has room:
@@ -375,19 +383,19 @@ int ngdbf_server_commit(ngdbf_server *server, int32_t n, const uint64_t *tickets
  * loaded stream.  What does not fit waits for a later pump.  Never blocks on
  * the device.
  */
-int ngdbf_server_pump(ngdbf_server *server, int32_t *n_launched);
+ngdbf_status ngdbf_server_pump(ngdbf_server *server, int32_t *n_launched);
 /*
  * ngdbf_server_poll -- non-blocking: writes to tickets[0 .. *n_done) the
  * requests whose launch has finished, in launch order, at most `capacity`.
  */
-int ngdbf_server_poll(ngdbf_server *server, int32_t capacity, uint64_t *tickets,
+ngdbf_status ngdbf_server_poll(ngdbf_server *server, int32_t capacity, uint64_t *tickets,
                       int32_t *n_done);
 /*
  * ngdbf_server_release -- return finished requests' slots to their pools.  The
  * client's reads of the outputs must be complete, or queued on the stream it
  * commits later requests on.
  */
-int ngdbf_server_release(ngdbf_server *server, int32_t n, const uint64_t *tickets);
+ngdbf_status ngdbf_server_release(ngdbf_server *server, int32_t n, const uint64_t *tickets);
 
 /*
  * ngdbf_objective -- the GDBF objective of Sec. III-B, f(x) = sum_k x_k y_k +
@@ -401,7 +409,7 @@ int ngdbf_server_release(ngdbf_server *server, int32_t n, const uint64_t *ticket
  *   out       : dev int64 [n_frames].
  * Errors: NGDBF_EINVAL (NULL code or buffers, n_frames < 0, bad y_format).
  */
-int ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format,
+ngdbf_status ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format,
                     int64_t n_frames, float ymax, const uint8_t *bits, int64_t *out,
                     void *stream);
 

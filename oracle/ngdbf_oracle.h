@@ -26,7 +26,8 @@ extern "C" {
 /* Decoder parameters (paper Sec. III-B..III-E, Sec. IV-A). */
 typedef struct {
     float w;             /* syndrome weight w (Sec. III-C, Step 2)              */
-    float theta;         /* initial inversion threshold theta < 0 (Step 0, 3b) */
+    float theta;         /* initial inversion threshold theta (Step 0, 3b; the
+                            paper takes theta < 0, any finite value decodes) */
     float lambda;        /* threshold adaptation factor, 0 < lambda <= 1;
                             lambda == 1 is the non-adaptive decoder (III-D)     */
     float eta;           /* perturbation scale: std of q_k is eta*sigma (III-C) */

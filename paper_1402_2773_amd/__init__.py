@@ -33,6 +33,9 @@ ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "
 
 NGDBF_MULTI, NGDBF_SINGLE, NGDBF_MODE_SWITCH = 0, 1, 2
 
+#: ngdbf_status values
+NGDBF_OK, NGDBF_EINVAL, NGDBF_ENOMEM, NGDBF_EDEVICE, NGDBF_EUNSUPPORTED, NGDBF_EBUSY = 0, -1, -2, -3, -4, -5
+
 
 class NgdbfError(RuntimeError):
     def __init__(self, status: int, message: str):
@@ -99,7 +102,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, U32, U64, F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float)
-        L.ngdbf_create_code.argtypes = [I32, I32, P, P, ctypes.POINTER(ctypes.c_void_p)]
+        L.ngdbf_create_code.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(ctypes.c_void_p)]
         L.ngdbf_destroy_code.argtypes = [P]
         L.ngdbf_code_info.argtypes = [P, P, P, P]
         L.ngdbf_decode.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, U64,
@@ -161,13 +164,15 @@ def _stream(stream) -> Optional[int]:
 
 # ------------------------------------------------------------- C entry points
 
-def ngdbf_create_code(n: int, m: int, row_ptr, col_idx) -> ctypes.c_void_p:
+def ngdbf_create_code(n: int, m: int, row_ptr, col_idx, nnz: Optional[int] = None) -> ctypes.c_void_p:
+    """nnz defaults to len(col_idx) (the library checks it against row_ptr[m])."""
     import numpy as np
 
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     h = ctypes.c_void_p()
-    _check(lib().ngdbf_create_code(n, m, rp.ctypes.data, ci.ctypes.data, ctypes.byref(h)))
+    _check(lib().ngdbf_create_code(n, m, len(ci) if nnz is None else nnz, rp.ctypes.data,
+                                   ci.ctypes.data, ctypes.byref(h)))
     return h
 
 

@@ -112,19 +112,22 @@ namespace {
 
 thread_local char g_err[512] = "";
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int fail(int code, const char *fmt, ...) {
+ngdbf_status fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ngdbf_status fail(int code, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  return code;
+  return (ngdbf_status)code;
 }
 
-int ok() {
+ngdbf_status ok() {
   g_err[0] = '\0';
   return NGDBF_OK;
 }
+
+// an internal status as the ABI's type
+ngdbf_status st(int rc) { return (ngdbf_status)rc; }
 
 }  // namespace
 
@@ -157,8 +160,10 @@ using ngdbf_host::Shape;
 // queues from a ring of kQueueSlots, launches recorded into a graph from a
 // ring of kCapturedSlots of their own, so that a graph's queues are never
 // those of direct launches running beside its replays.  Launches in flight
-// together take different queues; a graph must not be replayed on two
-// streams at the same time.
+// together take different queues: an event recorded after each direct launch
+// marks its queue free again, and a launch whose ring slot is still held
+// fails with NGDBF_EBUSY instead of sharing it.  A graph must not be replayed
+// on two streams at the same time.
 constexpr int kQueueSlots = 1024;
 constexpr int kCapturedSlots = 1024;
 
@@ -166,6 +171,8 @@ struct DeviceState {
   int cus = 0;
   // kQueueSlots + kCapturedSlots queues, allocated with the first code
   unsigned long long *queues = nullptr;
+  // one event per direct-ring queue, recorded on the launch's stream after it
+  std::vector<hipEvent_t> queue_done;
   std::atomic<uint32_t> next_queue{0};     // direct launches
   std::atomic<uint32_t> next_captured{0};  // launches recorded under stream capture
   std::mutex mu;                      // guards the fork/join pool below
@@ -208,16 +215,55 @@ int ensure_queues(int dev) {
     (void)hipFree(q);
     return fail(NGDBF_EDEVICE, "clearing the frame queues failed");
   }
+  std::vector<hipEvent_t> evs((size_t)kQueueSlots, nullptr);
+  for (auto &e : evs) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto &e2 : evs)
+        if (e2) (void)hipEventDestroy(e2);
+      (void)hipFree(q);
+      return fail(NGDBF_EDEVICE, "cannot create the frame queue events");
+    }
+  }
+  st.queue_done = std::move(evs);
   st.queues = q;  // kept until the process ends
   return NGDBF_OK;
 }
 
-unsigned long long *take_queue(int dev, bool captured) {
+// The queue of the next launch: ring slot *slot (-1 for a captured launch,
+// whose graph replays the device cannot see from here).  A direct-ring slot
+// whose previous launch has not finished is refused (NGDBF_EBUSY).
+int take_queue(int dev, bool captured, unsigned long long **queue, int *slot) {
   DeviceState &st = device_state(dev);
-  if (!st.queues) return nullptr;
-  const uint32_t i = captured ? (uint32_t)kQueueSlots + st.next_captured.fetch_add(1u) % (uint32_t)kCapturedSlots
-                              : st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
-  return st.queues + (size_t)ngdbf::kQueueWords * i;
+  if (!st.queues) return fail(NGDBF_EDEVICE, "no frame queues on device %d", dev);
+  if (captured) {
+    const uint32_t i = (uint32_t)kQueueSlots + st.next_captured.fetch_add(1u) % (uint32_t)kCapturedSlots;
+    *queue = st.queues + (size_t)ngdbf::kQueueWords * i;
+    *slot = -1;
+    return NGDBF_OK;
+  }
+  const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
+  // an earlier error is left for the caller to report; the query's own
+  // "not ready" is not an error and is cleared here
+  if (hipPeekAtLastError() == hipSuccess) {
+    const hipError_t q = hipEventQuery(st.queue_done[i]);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();
+      return fail(NGDBF_EBUSY, "all %d frame queues of device %d are held by launches in flight",
+                  kQueueSlots, dev);
+    }
+    if (q != hipSuccess) return fail(NGDBF_EDEVICE, "frame queue event: %s", hipGetErrorString(q));
+  }
+  *queue = st.queues + (size_t)ngdbf::kQueueWords * i;
+  *slot = (int)i;
+  return NGDBF_OK;
+}
+
+// mark a direct launch's queue as held until the work queued on s so far ends
+int hold_queue(int dev, int slot, hipStream_t s) {
+  if (slot < 0) return NGDBF_OK;
+  if (hipEventRecord(device_state(dev).queue_done[(size_t)slot], s) != hipSuccess)
+    return fail(NGDBF_EDEVICE, "frame queue event record failed");
+  return NGDBF_OK;
 }
 
 // Whether work queued on `s` now is recorded into a graph.  With an earlier
@@ -455,6 +501,7 @@ struct Prepared {
   Shape sh;
   size_t lds;
   int dev;
+  int queue_slot;  // direct-ring slot of the launch's queue, -1 if captured
   int y_format;
   bool ext;
   bool packed;
@@ -532,8 +579,8 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.fc_off = plan.fc_off;
   a.fc_bytes = p->t_max <= 255 ? 1 : 0;
   a.stats = code->stats;
-  a.queue = take_queue(dev, captured);
-  if (!a.queue) return fail(NGDBF_EDEVICE, "no frame queues on device %d", dev);
+  rc = take_queue(dev, captured, &a.queue, &out->queue_slot);
+  if (rc) return rc;
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;
@@ -562,8 +609,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   return ok();
 }
 
-int enqueue(const Prepared &pr, hipStream_t s) {
-  if (pr.a.n_frames == 0) return ok();
+int launch_prepared(const Prepared &pr, hipStream_t s) {
   const bool trace = pr.a.trace != nullptr;
   using ngdbf_host::dispatch;
   if (pr.ext) {
@@ -582,6 +628,14 @@ int enqueue(const Prepared &pr, hipStream_t s) {
   }
   return trace ? dispatch<NGDBF_Y_F32, true, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s)
                : dispatch<NGDBF_Y_F32, false, kBase>(pr.sh, pr.a, pr.lds, pr.dev, s);
+}
+
+// launch, then hold the launch's queue until it has run
+int enqueue(const Prepared &pr, hipStream_t s) {
+  if (pr.a.n_frames == 0) return ok();
+  const int rc = launch_prepared(pr, s);
+  if (rc) return rc;
+  return hold_queue(pr.dev, pr.queue_slot, s);
 }
 
 int pending_error() {
@@ -617,18 +671,21 @@ extern "C" {
 
 const char *ngdbf_last_error(void) { return g_err; }
 
-int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_t *col_idx,
-                      ngdbf_code **out) {
+ngdbf_status ngdbf_create_code(int32_t n, int32_t m, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col_idx, ngdbf_code **out) {
   if (!out) return fail(NGDBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!row_ptr || !col_idx) return fail(NGDBF_EINVAL, "row_ptr and col_idx are required");
   if (m < 1 || n <= m || n > 65535) return fail(NGDBF_EINVAL, "need 1 <= m < n <= 65535");
+  if (nnz < m) return fail(NGDBF_EINVAL, "nnz = %lld: every one of the %d rows needs an edge", (long long)nnz, m);
+  if (nnz > (1 << 24)) return fail(NGDBF_EUNSUPPORTED, "nnz %lld exceeds 2^24", (long long)nnz);
   if (row_ptr[0] != 0) return fail(NGDBF_EINVAL, "row_ptr[0] must be 0");
   for (int i = 0; i < m; ++i) {
     if (row_ptr[i + 1] <= row_ptr[i]) return fail(NGDBF_EINVAL, "row %d is empty or row_ptr decreases", i);
+    if (row_ptr[i + 1] > nnz) return fail(NGDBF_EINVAL, "row_ptr[%d] = %d exceeds nnz = %lld", i + 1, row_ptr[i + 1], (long long)nnz);
   }
-  const int64_t nnz = row_ptr[m];
-  if (nnz > (1 << 24)) return fail(NGDBF_EUNSUPPORTED, "nnz %lld exceeds 2^24", (long long)nnz);
+  if (row_ptr[m] != nnz)
+    return fail(NGDBF_EINVAL, "row_ptr[m] = %d differs from nnz = %lld", row_ptr[m], (long long)nnz);
   std::vector<int32_t> colcnt(n + 1, 0);
   for (int i = 0; i < m; ++i) {
     for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
@@ -696,7 +753,7 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   const size_t bytes = (size_t)words * 4;
   if (int qrc = ensure_queues(dev)) {
     free(c);
-    return qrc;
+    return st(qrc);
   }
   if (hipMalloc((void **)&c->d_tables, bytes) != hipSuccess) {
     free(c);
@@ -711,7 +768,7 @@ int ngdbf_create_code(int32_t n, int32_t m, const int32_t *row_ptr, const int32_
   return ok();
 }
 
-int ngdbf_destroy_code(ngdbf_code *code) {
+ngdbf_status ngdbf_destroy_code(ngdbf_code *code) {
   if (!code) return ok();
   const hipError_t e = hipFree(code->d_tables);
   free(code);
@@ -719,7 +776,7 @@ int ngdbf_destroy_code(ngdbf_code *code) {
   return ok();
 }
 
-int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m, int32_t *nnz) {
+ngdbf_status ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m, int32_t *nnz) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   if (n) *n = code->n;
   if (m) *m = code->m;
@@ -727,25 +784,25 @@ int ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m, int32_t *nnz
   return ok();
 }
 
-int ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+ngdbf_status ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
                  float sigma_scalar, const ngdbf_params *params, uint64_t seed,
                  uint64_t frame_base, uint8_t *out_bits, int32_t *out_iters,
                  uint8_t *out_converged, void *stream) {
-  return decode_common(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits,
-                       out_iters, out_converged, nullptr, stream);
+  return st(decode_common(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits,
+                          out_iters, out_converged, nullptr, stream));
 }
 
-int ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+ngdbf_status ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
                        float sigma_scalar, const ngdbf_params *params, uint64_t seed,
                        uint64_t frame_base, uint8_t *out_bits, int32_t *out_iters,
                        uint8_t *out_converged, uint8_t *flip_masks, void *stream) {
   if (n_frames > 0 && params && params->t_max > 0 && !flip_masks)
     return fail(NGDBF_EINVAL, "flip_masks is required");
-  return decode_common(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits,
-                       out_iters, out_converged, flip_masks ? flip_masks : nullptr, stream);
+  return st(decode_common(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits,
+                          out_iters, out_converged, flip_masks ? flip_masks : nullptr, stream));
 }
 
-int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t seed, uint64_t frame,
+ngdbf_status ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t seed, uint64_t frame,
                       uint32_t iter, float *out0, float *out1, void *stream) {
   if (count == 0) return ok();
   if (!out0) return fail(NGDBF_EINVAL, "out0 is NULL");
@@ -772,7 +829,7 @@ int ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t see
   return ok();
 }
 
-int ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format, int64_t n_frames,
+ngdbf_status ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format, int64_t n_frames,
                     float ymax, const uint8_t *bits, int64_t *out, void *stream) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   if (n_frames < 0) return fail(NGDBF_EINVAL, "n_frames < 0");
@@ -781,7 +838,7 @@ int ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format, int
   if (n_frames == 0) return ok();
   if (!y || !bits || !out) return fail(NGDBF_EINVAL, "y, bits and out are required");
   int rc = pending_error();
-  if (rc) return rc;
+  if (rc) return st(rc);
   const int per_block = 4;  // frames (wavefronts) per workgroup
   const int64_t blocks = (n_frames + per_block - 1) / per_block;
   if (blocks > 0x7FFFFFFF) return fail(NGDBF_EINVAL, "too many frames for one launch");
@@ -793,7 +850,7 @@ int ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_format, int
   return ok();
 }
 
-int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool, const float *sigma_pool,
+ngdbf_status ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool, const float *sigma_pool,
                           float sigma_scalar, int64_t pool_frames, const ngdbf_params *params,
                           const ngdbf_segment *segments, int32_t n_segments, int64_t n_frames,
                           uint8_t *bits_pool, int32_t *iters_pool, uint8_t *conv_pool,
@@ -805,13 +862,13 @@ int ngdbf_decode_segments(const ngdbf_code *code, const void *y_pool, const floa
   int rc = prepare(code, y_pool, n_frames, sigma_pool, sigma_scalar, params, 0, 0, bits_pool,
                    iters_pool, conv_pool, nullptr, nullptr, &pr, stream_capturing((hipStream_t)stream),
                    segments, n_segments, pool_frames);
-  if (rc) return rc;
+  if (rc) return st(rc);
   rc = pending_error();
-  if (rc) return rc;
-  return enqueue(pr, (hipStream_t)stream);
+  if (rc) return st(rc);
+  return st(enqueue(pr, (hipStream_t)stream));
 }
 
-int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quads_per_lane,
+ngdbf_status ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quads_per_lane,
                          int32_t frames_per_block) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   if (!waves_per_frame && !quads_per_lane && !frames_per_block) {
@@ -820,41 +877,41 @@ int ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame, int32_t quad
   }
   const Shape sh{waves_per_frame, quads_per_lane, frames_per_block};
   int rc = check_shape(code, sh, Layout{});
-  if (rc) return rc;
+  if (rc) return st(rc);
   code->shape[0] = sh.wpf;
   code->shape[1] = sh.qpl;
   code->shape[2] = sh.fpb;
   return ok();
 }
 
-int ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters) {
+ngdbf_status ngdbf_code_set_stats(ngdbf_code *code, uint64_t *counters) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   code->stats = counters;
   return ok();
 }
 
-int ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params, int32_t shape[3]) {
+ngdbf_status ngdbf_code_get_shape(const ngdbf_code *code, const ngdbf_params *params, int32_t shape[3]) {
   if (!code || !shape) return fail(NGDBF_EINVAL, "code and shape are required");
   if (params) {
-    if (int rc = check_params(params)) return rc;
+    if (int rc = check_params(params)) return st(rc);
   }
   Shape sh;
   int rc = pick_shape(code, params ? layout_of(code, params, false) : Layout{}, &sh);
-  if (rc) return rc;
+  if (rc) return st(rc);
   shape[0] = sh.wpf;
   shape[1] = sh.qpl;
   shape[2] = sh.fpb;
   return ok();
 }
 
-int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
+ngdbf_status ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const float *sigma,
                    float sigma_scalar, const ngdbf_params *params, uint64_t seed, int32_t best[3],
                    float *elapsed_ms, void *stream) {
   if (!code) return fail(NGDBF_EINVAL, "code is NULL");
   if (n_frames <= 0) return fail(NGDBF_EINVAL, "autotuning needs a sample of frames");
-  if (int prc = check_params(params)) return prc;
+  if (int prc = check_params(params)) return st(prc);
   int rc = pending_error();
-  if (rc) return rc;
+  if (rc) return st(rc);
   hipStream_t s = (hipStream_t)stream;
   const size_t nb = (size_t)(code->n + 7) / 8;
   uint8_t *bits = nullptr;
@@ -910,7 +967,7 @@ int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const floa
   (void)hipEventDestroy(e1);
   (void)hipFree(bits);
   (void)hipFree(iters);
-  if (rc) return rc;
+  if (rc) return st(rc);
   if (!best_sh.wpf) return fail(NGDBF_EUNSUPPORTED, "no launch shape fits this code");
   code->shape[0] = best_sh.wpf;
   code->shape[1] = best_sh.qpl;
@@ -924,11 +981,16 @@ int ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, const floa
   return ok();
 }
 
-int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
+ngdbf_status ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(NGDBF_EINVAL, "bad job array");
-  std::vector<Prepared> prs((size_t)n_jobs);
   // the library streams join a capture of `stream` through the fork event
   const bool captured = n_jobs > 0 && stream_capturing((hipStream_t)stream);
+  // every job takes its own frame queue before any is launched: a batch may
+  // not wrap its ring
+  if (n_jobs > (captured ? kCapturedSlots : kQueueSlots))
+    return fail(NGDBF_EINVAL, "%d jobs exceed the %d frame queues of one batch", n_jobs,
+                captured ? kCapturedSlots : kQueueSlots);
+  std::vector<Prepared> prs((size_t)n_jobs);
   for (int i = 0; i < n_jobs; ++i) {
     const ngdbf_job &j = jobs[i];
     const int rc = prepare(j.code, j.y, j.n_frames, j.sigma, j.sigma_scalar, &j.params, j.seed,
@@ -942,10 +1004,10 @@ int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
     if (i && prs[i].dev != prs[0].dev) return fail(NGDBF_EINVAL, "jobs span several devices");
   }
   int rc = pending_error();
-  if (rc) return rc;
+  if (rc) return st(rc);
   hipStream_t s = (hipStream_t)stream;
   if (n_jobs == 0) return ok();
-  if (n_jobs == 1) return enqueue(prs[0], s);
+  if (n_jobs == 1) return st(enqueue(prs[0], s));
   // A job of kFullJob frames or more fills the device by itself (its
   // persistent grid is the resident capacity): such jobs run one after another
   // on `stream`; the smaller ones run concurrently beside them on library
@@ -956,7 +1018,7 @@ int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
   if (small.empty()) {
     for (int i : large) {
       rc = enqueue(prs[i], s);
-      if (rc) return rc;
+      if (rc) return st(rc);
     }
     return ok();
   }
@@ -990,7 +1052,7 @@ int ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream) {
         hipStreamWaitEvent(s, ds.events[l], 0) != hipSuccess)
       return fail(NGDBF_EDEVICE, "join failed");
   }
-  return rc;
+  return st(rc);
 }
 
 }  // extern "C"

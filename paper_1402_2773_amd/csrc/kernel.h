@@ -398,14 +398,15 @@ struct Tables {
 // Exactness of the bound.  With m = (a >> 8) + 1 = f 2^e, u1 >= 2^(e-24), so
 // the radius is at most sqrt(2 (24 - e) ln 2) (the computed radius exceeds it
 // by less than 1e-7 relative), and |z| <= radius since |cos|, |sin| <= 1.
-// If a_k - theta_k >= qs * bound, every draw gives E_k >= theta_k (fma
+// If a_k - theta_k >= |qs| * bound, every draw gives E_k >= theta_k (fma
 // rounding is monotone and theta_k is a float): no flip, and the pair needs
 // no transform.  The extended kernels test this on squares with a 4e-5
 // relative slack that covers all rounding.  The base kernel compares a_k with
-// T_c = next_up(fl(theta_t + B_c)) >= theta_t + B_c exactly, where c =
-// clz(a | 1), B_c = next_up(fl(qs s_c)) >= qs s_c and s_c is the bound for c
-// leading zeros with 2e-5 slack; theta_k <= theta_t, so a_k >= T_c implies
-// a_k - theta_k >= qs * bound.  Every other pair goes through the transform.
+// T_c = next_up(fl(theta_max + B_c)) >= theta_max + B_c exactly, where c =
+// clz(a | 1), B_c = next_up(fl(|qs| s_c)) >= |qs| s_c, s_c is the bound for c
+// leading zeros with 2e-5 slack and theta_max >= theta_k for every bit (see
+// the threshold table below), so a_k >= T_c implies a_k - theta_k >= |qs| *
+// bound.  Every other pair goes through the transform.
 //
 // Wave priorities (base kernel): within a round the dense draw-and-settle
 // phase runs at the highest priority, the syndrome update next, the round's
@@ -485,9 +486,12 @@ decode_kernel(DecodeArgs a) {
   constexpr bool QR = EXT == kExtQuantReuse;
   // The base decoder keeps no per-bit thresholds.  A bit that has flipped F
   // times in rounds 0 .. t-1 has theta_k = theta lambda^(t - F) (Sec. III-D,
-  // by repeated binary32 multiplication); every bit that never flipped has
-  // theta_t = theta lambda^t, and theta_k <= theta_t for all.  The settle test
-  // uses theta_t (conservative); a listed bit's own theta_k comes from the
+  // by repeated binary32 multiplication, 0 < lambda <= 1); every bit that
+  // never flipped has theta_t = theta lambda^t.  Rounding is monotone, so the
+  // table theta lambda^u is non-decreasing in u for theta <= 0 and
+  // non-increasing for theta > 0: every theta_k is at most theta_max(t) =
+  // theta_t (theta <= 0) or theta (theta > 0).  The settle test uses
+  // theta_max(t) (conservative); a listed bit's own theta_k comes from the
   // table theta lambda^u (u = 0..T, LDS) and the frame's flip counts.
   constexpr bool LZ = EXT == kExtNone;
   const bool adapt = a.lambda != 1.0f;
@@ -590,8 +594,9 @@ decode_kernel(DecodeArgs a) {
     // floored at 2^-100 so that the settle test below stays strict: a margin
     // whose square underflows is never taken as settled
     const float bound_c = fmaxf((qs * qs) * 0x1.62e8p+0f, 0x1p-100f);
-    // LZ: B_c >= qs s_c exactly, and theta_t of round 0
-    const float bcl = (LZ || BB) ? next_up(qs * s_lane) : 0.0f;
+    // LZ: B_c >= |qs| s_c exactly (a negative sigma draws -qs z, whose
+    // magnitude has the same bound), and theta_t of round 0
+    const float bcl = (LZ || BB) ? next_up(fabsf(qs) * s_lane) : 0.0f;
     float tht = a.theta;
     // LZ: the frame's Philox counter words (wave-uniform) and the per-lane
     // part of every quad's first rounds, computed once per frame
@@ -1017,9 +1022,11 @@ decode_kernel(DecodeArgs a) {
             flush_list(list, lane, n_listed, qs, pend_, posb_, flip, quant, a.qc, a.qtop);
         };
         // LZ: lane c holds this round's settle threshold for a pair whose
-        // first word has c leading zeros, the float above theta_t + B_c
+        // first word has c leading zeros, the float above theta_max + B_c,
+        // with theta_max the largest threshold a bit can hold in round t:
+        // theta_t for theta <= 0, theta itself for theta > 0
         if (LZ) __builtin_amdgcn_s_setprio(kPrioDense);
-        const float tl = LZ ? next_up(tht + bcl) : 0.0f;
+        const float tl = LZ ? next_up((a.theta > 0.0f ? a.theta : tht) + bcl) : 0.0f;
         const PhiloxRound pr = philox_round((uint32_t)t, fr_lo, key0, key1);
         uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
         uint64_t posb = 0;     // list slot of each waiting pair, one byte each

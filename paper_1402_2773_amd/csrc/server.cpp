@@ -31,14 +31,14 @@ int set_error(int code, const char *msg);  // decode.hip: the per-thread message
 namespace {
 
 // Failures are reported through ngdbf_last_error, like every other call.
-int sfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-int sfail(int code, const char *fmt, ...) {
+ngdbf_status sfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+ngdbf_status sfail(int code, const char *fmt, ...) {
   char msg[512];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(msg, sizeof msg, fmt, ap);
   va_end(ap);
-  return ngdbf_host::set_error(code, msg);
+  return (ngdbf_status)ngdbf_host::set_error(code, msg);
 }
 
 // First-fit allocator of contiguous slot ranges, coalescing on release.
@@ -157,7 +157,7 @@ void destroy_server(ngdbf_server *s) {
 
 extern "C" {
 
-int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_params *params,
+ngdbf_status ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_params *params,
                         const int64_t *pool_frames, int32_t n_streams,
                         int32_t max_requests_per_launch, int32_t launches_per_stream,
                         ngdbf_server **out) {
@@ -230,12 +230,12 @@ int ngdbf_server_create(int32_t n_codes, ngdbf_code *const *codes, const ngdbf_p
   return NGDBF_OK;
 }
 
-int ngdbf_server_destroy(ngdbf_server *server) {
+ngdbf_status ngdbf_server_destroy(ngdbf_server *server) {
   if (server) destroy_server(server);
   return NGDBF_OK;
 }
 
-int ngdbf_server_pools(ngdbf_server *s, int32_t code_index, float **y, float **sigma,
+ngdbf_status ngdbf_server_pools(ngdbf_server *s, int32_t code_index, float **y, float **sigma,
                        uint8_t **bits, int32_t **iters, uint8_t **converged) {
   if (!s || code_index < 0 || code_index >= (int)s->pools.size())
     return sfail(NGDBF_EINVAL, "bad server or code index");
@@ -248,7 +248,7 @@ int ngdbf_server_pools(ngdbf_server *s, int32_t code_index, float **y, float **s
   return NGDBF_OK;
 }
 
-int ngdbf_server_admit(ngdbf_server *s, int32_t n_requests, const int32_t *code_index,
+ngdbf_status ngdbf_server_admit(ngdbf_server *s, int32_t n_requests, const int32_t *code_index,
                        const int64_t *n_frames, const uint64_t *seed, const uint64_t *frame_base,
                        uint64_t *tickets, int64_t *first_slots, int32_t *n_admitted) {
   if (!s || n_requests < 0 || !n_admitted) return sfail(NGDBF_EINVAL, "bad arguments");
@@ -275,7 +275,7 @@ int ngdbf_server_admit(ngdbf_server *s, int32_t n_requests, const int32_t *code_
   return NGDBF_OK;
 }
 
-int ngdbf_server_commit(ngdbf_server *s, int32_t n, const uint64_t *tickets, void *stream) {
+ngdbf_status ngdbf_server_commit(ngdbf_server *s, int32_t n, const uint64_t *tickets, void *stream) {
   if (!s || n < 0 || (n > 0 && !tickets)) return sfail(NGDBF_EINVAL, "bad arguments");
   if (n == 0) return NGDBF_OK;
   std::lock_guard<std::mutex> g(s->mu);
@@ -299,7 +299,7 @@ int ngdbf_server_commit(ngdbf_server *s, int32_t n, const uint64_t *tickets, voi
   return NGDBF_OK;
 }
 
-int ngdbf_server_pump(ngdbf_server *s, int32_t *n_launched) {
+ngdbf_status ngdbf_server_pump(ngdbf_server *s, int32_t *n_launched) {
   if (!s) return sfail(NGDBF_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> g(s->mu);
   int launched = 0;
@@ -374,7 +374,7 @@ int ngdbf_server_pump(ngdbf_server *s, int32_t *n_launched) {
   return NGDBF_OK;
 }
 
-int ngdbf_server_poll(ngdbf_server *s, int32_t capacity, uint64_t *tickets, int32_t *n_done) {
+ngdbf_status ngdbf_server_poll(ngdbf_server *s, int32_t capacity, uint64_t *tickets, int32_t *n_done) {
   if (!s || capacity < 0 || !n_done || (capacity > 0 && !tickets))
     return sfail(NGDBF_EINVAL, "bad arguments");
   *n_done = 0;
@@ -401,7 +401,7 @@ int ngdbf_server_poll(ngdbf_server *s, int32_t capacity, uint64_t *tickets, int3
   return NGDBF_OK;
 }
 
-int ngdbf_server_release(ngdbf_server *s, int32_t n, const uint64_t *tickets) {
+ngdbf_status ngdbf_server_release(ngdbf_server *s, int32_t n, const uint64_t *tickets) {
   if (!s || n < 0 || (n > 0 && !tickets)) return sfail(NGDBF_EINVAL, "bad arguments");
   std::lock_guard<std::mutex> g(s->mu);
   for (int i = 0; i < n; ++i) {

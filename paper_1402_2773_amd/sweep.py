@@ -30,9 +30,10 @@ import paper_1402_2773_amd as ng  # noqa: E402
 
 def heuristic_params(ebn0: float) -> Dict:
     """SM-NGDBF of Sec. IV-A: theta = -0.9, eta = 0.95, lambda by Eb/N0 (0.99
-    below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 from 4.5), w = 0.75,
+    below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 from 4.25 dB: the paper's
+    setting at 4.25 and 4.5 dB, extended to higher SNR), w = 0.75,
     smoothing over the last 64 rounds, T = 300."""
-    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.5 else 0.90
+    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.25 else 0.90
     return dict(w=0.75, theta=-0.9, lam=lam, eta=0.95, ymax=2.5, t_max=300, smooth_window=64)
 
 

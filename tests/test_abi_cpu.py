@@ -24,7 +24,7 @@ def L():
 def _declared():
     with open(os.path.join(ROOT, "include", "ngdbf.h")) as f:
         src = f.read()
-    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(ngdbf_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:ngdbf_status|const char \*)\s*(ngdbf_\w+)\s*\(", src, re.M)))
 
 
 def test_header_declares_the_binding_functions():
@@ -156,3 +156,65 @@ def test_create_code_rejects_more_shapes(L):
         ng.ngdbf_create_code(4, 2, [1, 2, 4], [0, 1, 2, 3])
     with pytest.raises(ng.NgdbfError, match="need 1 <= m < n"):
         ng.ngdbf_create_code(70000, 2, [0, 1, 2], [0, 1])
+
+
+def _struct_fields(path, name):
+    """(type, field) pairs of `typedef struct { ... } name;` in a C header."""
+    with open(path) as f:
+        src = f.read()
+    body = re.search(r"typedef struct \{(.*?)\}\s*" + name + r"\s*;", src, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return [tuple(m) for m in re.findall(r"(float|int32_t)\s+(\w+)\s*;", body)]
+
+
+def test_oracle_params_agree_with_the_abi_params_field_by_field():
+    """The oracle's parameter block (oracle/ngdbf_oracle.h) and the ABI's
+    (include/ngdbf.h) hold the same fields with the same C types in the same
+    order; the ABI's one extra field, y_format, is a separate argument of the
+    oracle's decode.  The two Python mirrors carry the same values into them."""
+    import oracle
+
+    abi = _struct_fields(os.path.join(ROOT, "include", "ngdbf.h"), "ngdbf_params")
+    ref = _struct_fields(os.path.join(ROOT, "oracle", "ngdbf_oracle.h"), "ngdbf_ref_params")
+    assert [f for f in abi if f[1] != "y_format"] == ref
+    assert ("int32_t", "y_format") in abi
+    # the ctypes mirrors follow their headers (lambda is spelled lam in Python)
+    py = lambda n: "lam" if n == "lambda" else n  # noqa: E731
+    assert [f[0] for f in ng.ngdbf_params._fields_] == [py(n) for _, n in abi]
+    assert [f[0] for f in oracle._Params._fields_] == [py(n) for _, n in ref]
+    for (t, n), (fname, ctype) in zip(abi, ng.ngdbf_params._fields_):
+        assert ctype == (ctypes.c_float if t == "float" else ctypes.c_int32), n
+    # the same parameter values reach both structures
+    gp = ng.Params(w=0.5, theta=0.25, lam=0.875, eta=1.5, ymax=2.0, t_max=77, smooth_window=9,
+                   variant=1, quant_bits=3, noise_reuse=1)
+    assert dataclasses_fields(gp) == dataclasses_fields(oracle.Params())
+    rp = oracle.Params(**gp.__dict__)
+    gc, rc = gp.c(ng.NGDBF_Y_I8), rp.c()
+    for fname, _ in oracle._Params._fields_:
+        assert getattr(gc, fname) == getattr(rc, fname), fname
+    assert gc.y_format == ng.NGDBF_Y_I8
+
+
+def dataclasses_fields(obj):
+    import dataclasses
+
+    return [f.name for f in dataclasses.fields(obj)]
+
+
+def test_create_code_checks_nnz(L):
+    with pytest.raises(ng.NgdbfError, match="differs from nnz"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 4], [0, 1, 2, 3], nnz=5)
+    with pytest.raises(ng.NgdbfError, match="exceeds nnz"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 4], [0, 1, 2, 3], nnz=3)
+    with pytest.raises(ng.NgdbfError, match="every one of the 2 rows"):
+        ng.ngdbf_create_code(4, 2, [0, 2, 4], [0, 1, 2, 3], nnz=1)
+
+
+def test_batch_may_not_wrap_the_queue_ring(L):
+    """Every job of a batch takes its own frame queue before any is launched,
+    so a batch larger than the ring of 1024 queues is refused up front."""
+    p = ng.Params().c(ng.NGDBF_Y_F32)
+    jobs = [ng.ngdbf_job(None, None, 0, None, 0.5, p, 1, 0, None, None, None)] * 1025
+    with pytest.raises(ng.NgdbfError, match="1025 jobs exceed the 1024 frame queues") as e:
+        ng.ngdbf_decode_batch(jobs, 0)
+    assert e.value.status == ng.NGDBF_EINVAL

@@ -363,3 +363,36 @@ def test_threads_and_frame_base_do_not_change_results(oracle_lib, c96):
     c = oracle.decode(c96, y[50:120], sig, P_SM, seed=23, frame_base=50)
     assert (a.bits == b.bits).all() and (a.iters == b.iters).all()
     assert (a.bits[50:120] == c.bits).all() and (a.iters[50:120] == c.iters).all()
+
+
+@pytest.mark.parametrize("ebn0,lam,frames", [(3.0, 0.99, 2048), (3.5, 0.97, 3072)])
+def test_binary64_decoder_with_adaptation_and_smoothing(oracle_lib, ebn0, lam, frames):
+    """SM-NGDBF on C1008 (theta -0.9, eta 0.95, W 64, T 300; the headline point
+    is 3.5 dB): the binary32 decoder and the binary64 one (thresholds adapted
+    and smoothing sums kept in double, draws from the same Philox words) agree
+    in FER and BER within 99.9% intervals, their trajectories coincide on
+    almost every frame, and the frames that end unconverged (where smoothing
+    decides the output) give the same smoothed words.  Sec. IV-A simulates in
+    double precision; this pins the binary64 decoder's adaptive and smoothing
+    paths beside its plain one."""
+    c = codes.named_code("C1008")
+    sig = channel.sigma_from_ebn0(ebn0, c.rate)
+    y = channel.bpsk_awgn(frames, c.n, sig, seed=18)
+    p = oracle.Params(w=0.75, theta=-0.9, lam=lam, eta=0.95, ymax=2.5, t_max=300, smooth_window=64)
+    a = oracle.decode(c, y, sig, p, seed=19, threads=8)
+    b = oracle.decode(c, y, sig, p, seed=19, threads=8, f64=True)
+    ea = oracle.unpack_bits(a.bits, c.n).sum(1).astype(np.int64)
+    eb = oracle.unpack_bits(b.bits, c.n).sum(1).astype(np.int64)
+    z = 3.29
+    k = int((eb > 0).sum())
+    ph = k / frames
+    half = z * math.sqrt(ph * (1 - ph) / frames + z * z / (4 * frames * frames)) / (1 + z * z / frames)
+    mid = (ph + z * z / (2 * frames)) / (1 + z * z / frames)
+    assert mid - half <= (ea > 0).mean() <= mid + half
+    sd = math.sqrt((ea.var(ddof=1) + eb.var(ddof=1)) / frames)
+    assert abs(ea.mean() - eb.mean()) <= z * sd + 1e-12
+    same = a.iters == b.iters
+    assert same.mean() > 0.98
+    unconv = same & (a.converged == 0)
+    assert unconv.sum() >= 3, "some frames must reach T (smoothing in use)"
+    assert (a.bits[unconv] == b.bits[unconv]).all(axis=1).mean() > 0.9

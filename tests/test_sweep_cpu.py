@@ -10,9 +10,10 @@ def test_range_parsing():
 
 
 def test_heuristic_lambda_schedule():
-    """Sec. IV-A: lambda 0.99 below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 above."""
-    assert [sweep.heuristic_params(e)["lam"] for e in (2.0, 3.0, 3.5, 4.0, 4.5, 5.0)] == \
-        [0.99, 0.99, 0.97, 0.94, 0.90, 0.90]
+    """Sec. IV-A: lambda 0.99 below 3.5 dB, 0.97 at 3.5, 0.94 at 4.0, 0.90 at
+    4.25 and 4.5 dB (kept above)."""
+    assert [sweep.heuristic_params(e)["lam"] for e in (2.0, 3.0, 3.5, 4.0, 4.25, 4.5, 5.0)] == \
+        [0.99, 0.99, 0.97, 0.94, 0.90, 0.90, 0.90]
     assert sweep.heuristic_params(3.0)["smooth_window"] == 64
 
 
