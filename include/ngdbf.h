@@ -180,6 +180,30 @@ ngdbf_status ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n
                        uint8_t *flip_masks, void *stream);
 
 /*
+ * ngdbf_decode_noalloc -- ngdbf_decode for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same decode, bit for bit, with the launch's
+ * frame queue in a static device array of the library (`scratch`, one queue
+ * of 9 cache-line-padded counters, 1152 bytes, held by every device the
+ * library runs on until the process ends) instead of the per-device ring.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine; the code handle, y and the outputs are the caller's) and queues
+ * two kernels on `stream`: one that zeroes the scratch queue, then the decode.
+ * Arguments, layouts and errors as ngdbf_decode; no input size needs more
+ * scratch than the array holds, and a build whose launch would need more
+ * refuses with NGDBF_EUNSUPPORTED.  Every call on one device shares the same
+ * scratch queue: calls that overlap on one device (on different streams, or
+ * replays of a captured call beside another) race on it and may skip or
+ * repeat frames, so serialise them.
+ */
+ngdbf_status ngdbf_decode_noalloc(const ngdbf_code *code, const void *y, int64_t n_frames,
+                                  const float *sigma, float sigma_scalar,
+                                  const ngdbf_params *params, uint64_t seed,
+                                  uint64_t frame_base, uint8_t *out_bits,
+                                  int32_t *out_iters, uint8_t *out_converged,
+                                  void *stream);
+
+/*
  * ngdbf_noise_probe -- evaluate the decoder's own Gaussian-source pieces on
  * the device, for exhaustive comparison with an independent implementation.
  *   kind 0: out0[j] = rho(m) = sqrt(-2 ln(m 2^-24)) for m = start + j

@@ -23,7 +23,7 @@ NGDBF_Y_I8 = 1
 
 #: names of the C entry points (include/ngdbf.h)
 ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "ngdbf_decode",
-                 "ngdbf_decode_trace", "ngdbf_noise_probe", "ngdbf_code_set_shape",
+                 "ngdbf_decode_trace", "ngdbf_decode_noalloc", "ngdbf_noise_probe", "ngdbf_code_set_shape",
                  "ngdbf_code_get_shape", "ngdbf_code_set_stats", "ngdbf_autotune", "ngdbf_decode_batch",
                  "ngdbf_decode_segments", "ngdbf_server_create", "ngdbf_server_destroy",
                  "ngdbf_server_pools", "ngdbf_server_admit", "ngdbf_server_commit",
@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
                                    P, P, P, P]
         L.ngdbf_decode_trace.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64,
                                          U64, P, P, P, P, P]
+        L.ngdbf_decode_noalloc.argtypes = [P, P, I64, P, F, ctypes.POINTER(ngdbf_params), U64, U64,
+                                           P, P, P, P]
         L.ngdbf_noise_probe.argtypes = [I32, U32, U32, U64, U64, U32, P, P, P]
         L.ngdbf_code_set_shape.argtypes = [P, I32, I32, I32]
         L.ngdbf_code_get_shape.argtypes = [P, ctypes.POINTER(ngdbf_params), P]
@@ -200,6 +202,13 @@ def ngdbf_decode_trace(code, y, n_frames: int, sigma, sigma_scalar: float, param
                                     ctypes.byref(params), seed, frame_base, _addr(out_bits),
                                     _addr(out_iters), _addr(out_converged), _addr(flip_masks),
                                     _stream(stream)))
+
+
+def ngdbf_decode_noalloc(code, y, n_frames: int, sigma, sigma_scalar: float, params: ngdbf_params,
+                         seed: int, frame_base: int, out_bits, out_iters, out_converged, stream) -> None:
+    _check(lib().ngdbf_decode_noalloc(code, _addr(y), n_frames, _addr(sigma), sigma_scalar,
+                                      ctypes.byref(params), seed, frame_base, _addr(out_bits),
+                                      _addr(out_iters), _addr(out_converged), _stream(stream)))
 
 
 def ngdbf_noise_probe(kind: int, start: int, count: int, seed: int, frame: int, iteration: int,

@@ -198,6 +198,39 @@ DeviceState &device_state(int dev) {
 
 int ngdbf_host::device_cus(int dev) { return device_state(dev).cus; }
 
+// ------------------------------------------------- allocation-free decode
+
+namespace ngdbf {
+// Device scratch of ngdbf_decode_noalloc: one frame queue (kQueueWords
+// counters, 1152 bytes) in a static array, which every device that loads the
+// library holds until the process ends.  Every call on a device shares it.
+constexpr size_t kScratchWords = (size_t)kQueueWords;
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+}  // namespace ngdbf
+
+namespace {
+
+// The device address of `scratch` on device dev (the device current), looked
+// up once per device.  In host code the array's name is only a stand-in for
+// the symbol, never a device address: kernels and fills get this pointer.
+int scratch_address(int dev, unsigned long long **out) {
+  static std::mutex mu;
+  static std::vector<unsigned long long *> addr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)addr.size() <= dev) addr.resize((size_t)dev + 1, nullptr);
+  if (!addr[(size_t)dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(ngdbf::scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(NGDBF_EDEVICE, "scratch symbol address on device %d: %s", dev, hipGetErrorString(e));
+    addr[(size_t)dev] = (unsigned long long *)ptr;
+  }
+  *out = addr[(size_t)dev];
+  return NGDBF_OK;
+}
+
+}  // namespace
+
 namespace {
 
 // allocate (and zero) the device's frame queues once; not inside a capture
@@ -511,7 +544,8 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
             float sigma_scalar, const ngdbf_params *p, uint64_t seed, uint64_t frame_base,
             uint8_t *out_bits, int32_t *out_iters, uint8_t *out_conv, uint8_t *trace,
             const Shape *force, Prepared *out, bool captured, const ngdbf_segment *segments = nullptr,
-            int32_t n_segments = 0, int64_t pool_frames = -1) {
+            int32_t n_segments = 0, int64_t pool_frames = -1,
+            unsigned long long *fixed_queue = nullptr) {
   // host-side validation, parameters first (no device state is touched)
   int rc = check_params(p);
   if (rc) return rc;
@@ -579,8 +613,13 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.fc_off = plan.fc_off;
   a.fc_bytes = p->t_max <= 255 ? 1 : 0;
   a.stats = code->stats;
-  rc = take_queue(dev, captured, &a.queue, &out->queue_slot);
-  if (rc) return rc;
+  if (fixed_queue) {
+    a.queue = fixed_queue;
+    out->queue_slot = -1;
+  } else {
+    rc = take_queue(dev, captured, &a.queue, &out->queue_slot);
+    if (rc) return rc;
+  }
   a.stream_lr = packed_stream_lr(L);
   a.red_off = plan.red_off;
   a.stream_off = plan.stream_off;
@@ -800,6 +839,37 @@ ngdbf_status ngdbf_decode_trace(const ngdbf_code *code, const void *y, int64_t n
     return fail(NGDBF_EINVAL, "flip_masks is required");
   return st(decode_common(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits,
                           out_iters, out_converged, flip_masks ? flip_masks : nullptr, stream));
+}
+
+ngdbf_status ngdbf_decode_noalloc(const ngdbf_code *code, const void *y, int64_t n_frames,
+                                  const float *sigma, float sigma_scalar,
+                                  const ngdbf_params *params, uint64_t seed, uint64_t frame_base,
+                                  uint8_t *out_bits, int32_t *out_iters, uint8_t *out_converged,
+                                  void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(NGDBF_EDEVICE, "no HIP device");
+  unsigned long long *q = nullptr;
+  int rc = scratch_address(dev, &q);
+  if (rc) return st(rc);
+  // the launch needs one queue; nothing else of it depends on the batch size
+  static_assert(ngdbf::kScratchWords >= (size_t)ngdbf::kQueueWords, "scratch holds one queue");
+  const size_t need = (size_t)ngdbf::kQueueWords * sizeof(unsigned long long);
+  if (need > sizeof(ngdbf::scratch))
+    return fail(NGDBF_EUNSUPPORTED, "the launch needs %zu bytes of scratch, the library holds %zu",
+                need, sizeof(ngdbf::scratch));
+  Prepared pr;
+  rc = prepare(code, y, n_frames, sigma, sigma_scalar, params, seed, frame_base, out_bits, out_iters,
+               out_converged, nullptr, nullptr, &pr, false, nullptr, 0, -1, q);
+  if (rc) return st(rc);
+  rc = pending_error();
+  if (rc) return st(rc);
+  if (n_frames == 0) return ok();
+  // the queue's counters start at zero (the last launch's final taker also
+  // clears them, but a launch that never ran to its end would not have)
+  hipLaunchKernelGGL(ngdbf::clear_bytes_kernel, dim3(1), dim3(256), 0, s, (uint8_t *)q, need);
+  if (hipGetLastError() != hipSuccess) return fail(NGDBF_EDEVICE, "scratch clear failed");
+  return st(launch_prepared(pr, s));
 }
 
 ngdbf_status ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count, uint64_t seed, uint64_t frame,
