@@ -361,9 +361,18 @@ struct SlotPlan {
   int red_off = 0, stream_off = 0, clear_words = 0, slot_words = 0, fc_off = 0;
 };
 
+// Check-toggle events a frame lists per round for the parallel u update: one
+// per check (a round toggles each check at most once), within the exact range
+// of the kernel's division by d_c; irregular codes apply their toggles
+// directly and list none.
+int event_cap(const ngdbf_code *c) {
+  if (!c->dc) return 0;
+  return std::min(c->m, std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
+}
+
 SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
   int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 3 +
-          (c->m + 31) / 32 + ngdbf::kEventCap;
+          (c->m + 31) / 32 + event_cap(c);
   SlotPlan p;
   if (L.ext) {
     w = (w + 1) & ~1;
@@ -606,6 +615,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.xw_words = (n + 31) / 32;
   const SlotPlan plan = slot_plan(code, L);
   a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
+  a.event_cap = event_cap(code);
   a.slot_words = plan.slot_words;
   a.slots_off = slots_offset(code, L, sh);
   a.qtab_off = qtab_offset(code, L, sh);

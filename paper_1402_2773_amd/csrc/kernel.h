@@ -44,8 +44,6 @@ constexpr int kEntryWords = 6;
 // the pair's index (its thresholds are looked up when the list is finished)
 constexpr int kListCapLazy = 192;
 constexpr int kEntryWordsLazy = 5;
-// check-toggle events per frame and round held for the parallel u update
-constexpr int kEventCap = 256;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 // s_setprio levels of the round phases of the base kernel and of the packed
@@ -101,6 +99,8 @@ struct DecodeArgs {
   int32_t frames_per_block;               // frame slots per workgroup
   int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
   uint32_t dc_recip;                      // ceil(2^20 / d_c) for regular codes
+  int32_t event_cap;                      // check-toggle events per frame and round held
+                                          // for the parallel u update (0: irregular code)
   int32_t slot_words;                     // LDS words per frame slot (even)
   int32_t slots_off;                      // LDS word offset of the frame slots (even)
   // extended decoders (EXT kernels)
@@ -475,7 +475,7 @@ decode_kernel(DecodeArgs a) {
   uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
   uint32_t *evn = cnt + 1;                 // [2] events listed (rounds alternate)
   uint32_t *tw = evn + 2;                  // [sw_words] checks toggled this round
-  uint32_t *evl = tw + a.sw_words;         // [kEventCap] toggle events
+  uint32_t *evl = tw + a.sw_words;         // [event_cap] toggle events
   uint32_t *fcw = slot + a.fc_off;         // LZ: flip counts, four or two bits per word
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
@@ -1169,14 +1169,15 @@ decode_kernel(DecodeArgs a) {
         sw[wd] = sn;
         tw[wd] = 0u;
         dcnt += 2 * __builtin_popcount(sn & tg) - __builtin_popcount(tg);
-        uint32_t slotn = REG ? atomicAdd(evc, (uint32_t)__builtin_popcount(tg)) : (uint32_t)kEventCap;
+        const uint32_t ecap = (uint32_t)a.event_cap;
+        uint32_t slotn = REG ? atomicAdd(evc, (uint32_t)__builtin_popcount(tg)) : ecap;
         uint32_t bits = tg;
         while (bits) {
           const int bb = __builtin_ctz(bits);
           bits &= bits - 1;
           const int i = 32 * wd + bb;
           const bool unsat_now = ((sn >> bb) & 1u) != 0u;
-          if (slotn < (uint32_t)kEventCap) {
+          if (slotn < ecap) {
             evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
           } else {
             // list full (or an irregular code): apply the event here
@@ -1196,11 +1197,12 @@ decode_kernel(DecodeArgs a) {
         //    all lanes of the frame
         frame_sync<WPF>();
         const uint32_t nev = __hip_atomic_load(evc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const uint32_t listed = nev < (uint32_t)kEventCap ? nev : (uint32_t)kEventCap;
+        const uint32_t listed = nev < (uint32_t)a.event_cap ? nev : (uint32_t)a.event_cap;
         const uint32_t nup = listed * (uint32_t)a.dc;
         for (uint32_t x = (uint32_t)ft; x < nup; x += FT) {
-          // x / d_c, exact here; every product stays below 2^32 and its
-          // factors below 2^24
+          // x / d_c, exact here: x < event_cap d_c with event_cap d_c^2 <
+          // 2^20 (the reciprocal's error stays below one step) and event_cap
+          // < 4096 (x ceil(2^20 / d_c) stays below 2^32); factors below 2^24
           const uint32_t e = __umul24(x, a.dc_recip) >> 20;
           const uint32_t ev = evl[e];
           const int i = (int)(ev >> 1);
