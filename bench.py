@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
 """Throughput benchmark: batched NGDBF decoding on one MI355X.
 
-A step decodes one batch of synthetic received frames that is already
-resident in HBM: 2^20 frames of the (3,6) N=1008 code at Eb/N0 = 3.5 dB with
-the paper's heuristics (adaptive threshold and output smoothing, T = 300;
-Sec. III-D, III-E, IV-A).  It prints one JSON line with decoded information
-Gbit/s (the value), edge updates/s, BER/FER of the run, per-step latency, the
-dominant kernel's roofline position and the CPU oracle's rate on a sample.
+Default workload (one step = one batch resident in HBM): the batched
+multi-code launch of 2^22 received frames, codes N = 96, 1008, 2048 and 4000
+in frame proportions 4:2:1:1, Eb/N0 drawn per frame uniformly in 2..5 dB,
+each code with its own decoder parameters (Sec. IV-A), all frames decoded by
+one graph-captured ngdbf_decode_batch call.  It prints one JSON line with
+decoded information Gbit/s (the value), edge updates/s, BER/FER per code, the
+same frames decoded by plain per-code launches, per-step latency, the
+dominant kernel's roofline position, the single-code headline point (C1008
+SM-NGDBF at 3.5 dB) and the CPU oracle's rate on a sample of every code.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
 """
@@ -24,10 +27,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded info Gbit/s + edge-updates/s on 1 MI355X at fixed BER; p50/p99 decode latency"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = one VALU lane-operation per
-# lane and clock -> 39.3e12 lane-ops/s; HBM3E 8 TB/s.
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A wave64 vector-ALU instruction holds
+# its SIMD for ISSUE_CYCLES[class] clocks (measured by --workload issue-rates:
+# four for 32/64-bit integer, bitwise, shift and conversion instructions, two
+# for binary32 fma/mul/add, eight for transcendentals).  The issue ceiling is
+# counted in 4-clock slots of 64 lanes: 256 x 4 x 2.4e9 / 4 x 64 = 39.32e12
+# lane-op slots/s (an fp32 fma fills half a slot).
+PEAK_ISSUE_TSLOTS = 256 * 4 * 2.4e9 / 4 * 64 / 1e12
 PEAK_HBM_GBS = 8000.0
+ISSUE_CYCLES = {"SQ_INSTS_VALU_INT32": 4, "SQ_INSTS_VALU_INT64": 4, "SQ_INSTS_VALU_CVT": 4,
+                "SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_MUL_F32": 2, "SQ_INSTS_VALU_ADD_F32": 2,
+                "SQ_INSTS_VALU_TRANS_F32": 8, "other": 4}
+# LDS ceiling of the method's on-chip exchange (one bank access per edge
+# gather, 2 nnz gathers per frame-round, no bit slicing): 256 CUs x 32 banks
+# x 2.4 GHz of bank accesses; bit-iterations/s = that / (2 d_v)
+LDS_BANK_ACCESSES = 256 * 32 * 2.4e9
 
 
 def _heur(ebn0: float):
@@ -76,7 +90,8 @@ WORKLOADS = {
                                                 t_max=100, smooth_window=0, variant=1), 1 << 20, "f32",
                             "S-NGDBF (single-bit argmin flip), (3,6) N=1008, 3.5 dB, T=100"),
 }
-DEFAULT = "c1008_sm_3.5dB"
+HEADLINE = "c1008_sm_3.5dB"
+DEFAULT = "mix4"
 
 # launch shapes (waves per frame, quads per lane, frames per workgroup) for
 # workloads whose default shape is slower (none at present: the library's
@@ -90,16 +105,6 @@ MIX4 = [("C96", 1 << 21, _plain(100)), ("C1008", 1 << 20, _heur(3.5)),
                                 smooth_window=0)),
         ("C4000", 1 << 19, _heur(3.5))]
 
-# VALU lane-operations of one bit-iteration of the method as defined (one
-# E_k evaluation with its own Gaussian draw), counted on the gfx950 lowering:
-#   Philox4x32-10 per quad: 10 rounds x (2 mad_u64_u32 + 2 xor3) = 40 -> 10 / bit
-#   Box-Muller per pair: radius 36 (clz, ldexp, reduction, correctly rounded
-#   division 10, 6 fma, correctly rounded sqrt 6, ...) + angle 27 + 2 mul = 65
-#   -> 32.5 / bit
-#   E_k: d_v adds, convert, x*y, 2 fma, compare, threshold update = 10 / bit
-#   syndrome: m (d_c - 1) XORs per frame-iteration = (d_c - 1) m / n per bit
-VALU_OPS_PER_BIT_ITER = 10 + 32.5 + 10
-
 
 def kernel_sources_digest() -> str:
     """sha256 over the decoder's device sources (what a counter profile was taken of)."""
@@ -112,11 +117,12 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    profile of this workload, scaled by the same counters' reading for a plain
-    1 GiB copy; None if there is none or the kernel has changed since."""
-    path = os.path.join(ROOT, "profiles", f"decode_kernel_{workload}.traffic.json")
+def counter_profile(workload: str):
+    """Per-launch hardware counters of the workload's decode kernels from the
+    committed rocprofv3 profile (instruction classes, copy-calibrated HBM
+    bytes, kernel-trace averages), keyed by the kernel sources' hash; None if
+    there is none or the kernel has changed since."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -126,20 +132,42 @@ def measured_traffic(workload: str):
     return d
 
 
-# With noise reuse the method draws n samples to preload the chain and one
-# new sample per round; a round then costs E_k alone (10 per bit, 13 with the
-# quantized threshold g(theta_k)).
-VALU_OPS_PER_DRAW = 10 + 32.5
+def issue_slots(counters: dict) -> float:
+    """4-clock vector-ALU issue slots a launch fills: every instruction class
+    counted by its SQ counter, weighted by its issue time."""
+    classes = [k for k in ISSUE_CYCLES if k != "other"]
+    other = counters["SQ_INSTS_VALU"] - sum(counters.get(k, 0.0) for k in classes)
+    return (sum(counters.get(k, 0.0) * ISSUE_CYCLES[k] for k in classes) + other * ISSUE_CYCLES["other"]) / 4.0
 
 
-def algorithmic_valu_ops(code, bit_iters: float, params=None, frames: int = 0) -> float:
-    dc = code.nnz / code.m
-    syn = (dc - 1) * code.m / code.n
-    if params and params.get("noise_reuse"):
-        per_bit = (13 if params.get("quant_bits") else 10) + syn
-        draws = frames * code.n + bit_iters / code.n
-        return bit_iters * per_bit + draws * VALU_OPS_PER_DRAW
-    return bit_iters * (VALU_OPS_PER_BIT_ITER + syn)
+def roofline(code, frames: int, yfmt: str, kernel_ms: float, bit_iters: float, counters,
+             per_frame_sigma: bool, kernel: str) -> dict:
+    """The kernel's position against the vector-ALU issue ceiling (the bound:
+    every decode kernel here issues on nearly every SIMD clock), with the HBM
+    and LDS fractions of the method's algorithmic traffic beside it."""
+    ks = kernel_ms / 1e3
+    alg_bytes = frames * hbm_bytes_per_frame(code, yfmt, per_frame_sigma)
+    dv = code.nnz / code.n
+    lds_ceiling_bit_iters = LDS_BANK_ACCESSES / (2 * dv)
+    r = {"bound": "alu", "kernel": kernel, "kernel_ms": kernel_ms,
+         "unit": "T lane-op slots/s (4-clock wave64 issue slots x 64 lanes)",
+         "peak": PEAK_ISSUE_TSLOTS, "achieved": None, "frac": None, "traffic": None,
+         "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+         "algorithmic_bytes": alg_bytes, "hbm_achieved_GBs": alg_bytes / ks / 1e9,
+         "hbm_frac": alg_bytes / ks / 1e9 / PEAK_HBM_GBS,
+         "lds_frac_method": bit_iters / ks / lds_ceiling_bit_iters,
+         "lds_what": "bit-iterations/s against 256 CUs x 32 banks x 2.4 GHz / (2 d_v): the method's "
+                     "2 nnz edge gathers per frame-round at one bank access each"}
+    if counters:
+        slots = issue_slots(counters)
+        r["achieved"] = slots * 64 / ks / 1e12
+        r["frac"] = r["achieved"] / PEAK_ISSUE_TSLOTS
+        r["executed_valu_lane_ops_per_s"] = counters["SQ_INSTS_VALU"] * 64 / ks
+        r["valu_instructions_per_launch"] = counters["SQ_INSTS_VALU"]
+        if counters.get("traffic_bytes") is not None:
+            r["traffic"] = counters["traffic_bytes"]
+        r["counters_from"] = counters.get("source")
+    return r
 
 
 def hbm_bytes_per_frame(code, yfmt: str, per_frame_sigma: bool = False) -> int:
@@ -148,86 +176,126 @@ def hbm_bytes_per_frame(code, yfmt: str, per_frame_sigma: bool = False) -> int:
     return code.n * sy + (code.n + 7) // 8 + 4 + 1 + (4 if per_frame_sigma else 0)
 
 
-def cpu_baseline(code, y_host, sigma, params, seed, budget_s: float):
-    """The CPU oracle on a bounded sample of the same workload."""
-    import numpy as np
-
-    import oracle
-
-    oracle.build(force=False)
+def host_cpu():
+    """Host threads available to this process and the CPU model name."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def oracle_rate(code, y_host, sigma, params, seed, budget_s: float, cores: int):
+    """Frames/s of the CPU oracle on a bounded sample (frames in order from
+    the first), and the sample it ran."""
+    import numpy as np
+
+    import oracle
+
     p = oracle.Params(**params)
-    n0 = min(len(y_host), 64 * cores)
+    sig = sigma if np.ndim(sigma) == 0 else np.asarray(sigma, dtype=np.float32)
+    n0 = min(len(y_host), 16 * cores)
     t0 = time.perf_counter()
-    oracle.decode(code, y_host[:n0], np.float32(sigma), p, seed, threads=cores)
+    oracle.decode(code, y_host[:n0], sig if np.ndim(sig) == 0 else sig[:n0], p, seed, threads=cores)
     dt = time.perf_counter() - t0
     n1 = int(min(len(y_host), max(n0, n0 * budget_s / max(dt, 1e-3))))
     t0 = time.perf_counter()
-    r = oracle.decode(code, y_host[:n1], np.float32(sigma), p, seed, threads=cores)
+    r = oracle.decode(code, y_host[:n1], sig if np.ndim(sig) == 0 else sig[:n1], p, seed, threads=cores)
     dt = time.perf_counter() - t0
-    gbps = n1 * code.k_info / dt / 1e9
-    return {"value": gbps, "unit": "Gbit/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n1} of the workload's frames (same code, SNR, parameters), "
-                      f"{dt:.1f} s on {cores} host threads",
-            "edge_updates_per_s": float(r.iters.sum()) * code.nnz / dt}
+    return n1 / dt, n1, dt, float(r.iters.sum())
+
+
+def cpu_baseline(code, y_host, sigma, params, seed, budget_s: float):
+    """The CPU oracle on a bounded sample of the same workload, on every host
+    thread available."""
+    oracle_build()
+    cores, model = host_cpu()
+    fps, n1, dt, iters = oracle_rate(code, y_host, sigma, params, seed, budget_s, cores)
+    return {"value": fps * code.k_info / 1e9, "unit": "Gbit/s", "cores": cores, "cpu_model": model,
+            "kind": "oracle",
+            "sample": f"{n1} of the workload's frames (same code, SNR, parameters), {dt:.1f} s on "
+                      f"{cores} host threads",
+            "edge_updates_per_s": iters * code.nnz / dt}
+
+
+def oracle_build():
+    import oracle
+
+    oracle.build(force=False)
+
+
+def stats_of(ng, dev_code, out, t_max: int):
+    """Device counters of the decoded frames (ngdbf_frame_stats) as a dict."""
+    acc = ng.frame_stats(dev_code, out, t_max).cpu().tolist()
+    frames = out.bits.shape[0]
+    n = dev_code.n
+    return {"frames": frames, "avg_iterations": acc[4] / frames, "ber": acc[0] / (frames * n),
+            "fer": acc[2] / frames, "undetected": int(acc[3]), "unconverged_frames": int(acc[5]),
+            "iterations": int(acc[4])}
+
+
+def timed_steps(torch, fn, steps: int, warmup: int, stream):
+    """W untimed calls, then K timed ones bracketed by synchronisation; wall
+    ms per step and the per-step HIP-event times on `stream`."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    return wall, [e0.elapsed_time(e1) for e0, e1 in ev]
 
 
 def run_mix4(args) -> int:
-    """Batched decode of a mixed-code batch (one graph-captured batch call per
-    step) against plain sequential per-code launches of the same frames."""
+    """The batched multi-code launch: one graph replay of one
+    ngdbf_decode_batch call over the four codes' jobs per step; then the same
+    frames as plain per-code launches one after another (each timed with HIP
+    events on its stream: the per-kernel times the roofline uses)."""
     import numpy as np
     import torch
 
     import paper_1402_2773_amd as ng
+    from paper_1402_2773_amd import sweep
     from synth import channel, codes
 
     scale = args.frames / float(1 << 22) if args.frames else 1.0
+    stream = torch.cuda.current_stream()
     items = []
     for idx, (name, frames, params) in enumerate(MIX4):
         frames = max(1, int(frames * scale))
         c = codes.named_code(name)
-        sig = torch.from_numpy(channel.frame_sigmas(frames, 2.0, 5.0, c.rate, seed=300 + idx)).cuda()
-        y = channel.bpsk_awgn_device(frames, c.n, sig, seed=310 + idx)
+        sig_h = channel.frame_sigmas(frames, 2.0, 5.0, c.rate, seed=300 + idx)
+        sig = torch.from_numpy(sig_h).cuda()
+        y = ng.channel(c.n, frames, sig, seed=sweep.channel_seed(320 + idx))
         dc = ng.Code.from_ldpc(c)
         p = ng.Params(**params)
-        items.append(dict(name=name, c=c, dc=dc, y=y, sig=sig, p=p, seed=320 + idx, frames=frames,
-                          params=params, out=ng.alloc_outputs(dc, frames, "cuda"),
+        items.append(dict(name=name, c=c, dc=dc, y=y, sig=sig, sig_h=sig_h, p=p, seed=320 + idx,
+                          frames=frames, params=params, out=ng.alloc_outputs(dc, frames, "cuda"),
                           out_plain=ng.alloc_outputs(dc, frames, "cuda")))
     torch.cuda.synchronize()
 
-    # plain per-code launches: default shapes, one after another on one stream
-    def plain():
-        for it in items:
-            ng.decode(it["dc"], it["y"], it["sig"], it["p"], it["seed"], out=it["out_plain"])
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
-        t0 = time.perf_counter()
-        for e0, e1 in ev:
-            e0.record()
-            fn()
-            e1.record()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps * 1e3, [e0.elapsed_time(e1) for e0, e1 in ev]
-
-    plain_ms, _ = timed(plain, max(1, args.steps // 2), 1)
-
     # batched: one batch call captured into a graph (default shapes, or the
     # autotuner's choice on a sample with --mix-autotune)
-    tuned = {}
     for it in items:
         if args.mix_autotune:
             n_s = min(it["frames"], 1 << 17)  # several times the resident frames
-            best, ms = ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
-        tuned[it["name"]] = list(ng.ngdbf_code_get_shape(it["dc"].handle, it["p"].c(ng.NGDBF_Y_F32)))
+            ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
+        it["shape"] = list(ng.ngdbf_code_get_shape(it["dc"].handle, it["p"].c(ng.NGDBF_Y_F32)))
     jobs = [ng.job(it["dc"], it["y"], it["sig"], it["p"], it["seed"], it["out"]) for it in items]
     ng.ngdbf_decode_batch(jobs, None)
     torch.cuda.synchronize()
@@ -238,41 +306,81 @@ def run_mix4(args) -> int:
         with torch.cuda.graph(g, stream=cs):
             ng.ngdbf_decode_batch(jobs, cs)
     torch.cuda.synchronize()
-    batch_ms, step_ms = timed(g.replay, args.steps, args.warmup)
+    batch_ms, step_ms = timed_steps(torch, g.replay, args.steps, args.warmup, stream)
+
+    # plain per-code launches of the same frames, each kernel timed on its stream
+    per_code_ms = {}
+    for it in items:
+        def one(it=it):
+            ng.decode(it["dc"], it["y"], it["sig"], it["p"], it["seed"], out=it["out_plain"], stream=stream)
+        _, ms = timed_steps(torch, one, max(1, args.steps // 2), 1, stream)
+        per_code_ms[it["name"]] = float(np.mean(ms))
+    plain_ms = sum(per_code_ms.values())
 
     info_bits = sum(it["frames"] * it["c"].k_info for it in items)
-    per_code = {}
-    same = True
-    total_ops = 0.0
+    prof = counter_profile("mix4") if not args.frames else None
+    per_code, same = {}, True
+    total_iters, total_edges, total_bit_iters = 0, 0.0, 0.0
     for it in items:
-        bits = it["out"].bits.cpu().numpy()
-        errs = np.unpackbits(bits, axis=1, bitorder="little")[:, :it["c"].n]
-        iters = it["out"].iters.to(torch.int64)
-        same &= bool((it["out"].bits == it["out_plain"].bits).all().item()
-                     and (it["out"].iters == it["out_plain"].iters).all().item())
-        total_ops += algorithmic_valu_ops(it["c"], float(iters.sum().item()) * it["c"].n)
-        per_code[it["name"]] = {"frames": it["frames"], "avg_iterations": float(iters.double().mean().item()),
-                                "ber": float(errs.mean()), "fer": float((errs.sum(1) > 0).mean()),
-                                "shape": tuned[it["name"]]}
+        same &= bool(torch.equal(it["out"].bits, it["out_plain"].bits)
+                     and torch.equal(it["out"].iters, it["out_plain"].iters))
+        st = stats_of(ng, it["dc"], it["out"], it["params"]["t_max"])
+        total_iters += st["iterations"]
+        total_edges += st["iterations"] * it["c"].nnz
+        total_bit_iters += st["iterations"] * it["c"].n
+        ms = per_code_ms[it["name"]]
+        cnt = prof["instances"].get(it["name"]) if prof else None
+        rf = roofline(it["c"], it["frames"], "f32", ms, st["iterations"] * it["c"].n, cnt, True,
+                      f"decode_kernel<{','.join(map(str, it['shape'][:2]))},0,false,true,0>")
+        per_code[it["name"]] = {**st, "n": it["c"].n, "k": it["c"].k_info, "nnz": it["c"].nnz,
+                                "params": it["params"], "shape": it["shape"], "kernel_ms": ms,
+                                "info_gbps_plain": it["frames"] * it["c"].k_info / (ms / 1e3) / 1e9,
+                                "issue_frac": rf["frac"], "hbm_frac": rf["hbm_frac"]}
+        it["roofline"] = rf
+    dominant = max(items, key=lambda it: per_code_ms[it["name"]])
     value = info_bits / (batch_ms / 1e3) / 1e9
-    alu = total_ops / (float(np.mean(step_ms)) / 1e3) / 1e12
     result = {
         "metric": METRIC, "value": value, "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": batch_ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN, per-frame Eb/N0 ~ U[2,5] dB",
-        "config": {"workload": "mix4", "codes": {k: v for k, v in per_code.items()},
-                   "frames": sum(it["frames"] for it in items),
-                   "description": "one graph-captured batched launch of C96:C1008:C2048:C4000 = 4:2:1:1",
+        "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN from the device "
+                "channel (Philox), per-frame Eb/N0 ~ U[2,5] dB",
+        "config": {"workload": "mix4", "frames": sum(it["frames"] for it in items),
+                   "codes": {it["name"]: it["frames"] for it in items},
+                   "ebn0_db": "per frame U[2,5]",
+                   "description": "one graph-captured ngdbf_decode_batch of C96:C1008:C2048:C4000 = "
+                                  "4:2:1:1 (2^22 frames), per-code parameters (Sec. IV-A)",
                    "autotuned": bool(args.mix_autotune)},
-        "plain_per_code_launch": {"ms_per_step": plain_ms,
-                                  "value": info_bits / (plain_ms / 1e3) / 1e9,
+        "edge_updates_per_s": total_edges / (batch_ms / 1e3),
+        "bit_iterations_per_s": total_bit_iters / (batch_ms / 1e3),
+        "avg_iterations": total_iters / sum(it["frames"] for it in items),
+        "per_code": per_code,
+        "plain_per_code_launch": {"ms_per_step": plain_ms, "value": info_bits / (plain_ms / 1e3) / 1e9,
                                   "same_results_as_batched": same},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
                        "what": "one graph replay (the whole mixed batch)"},
-        "roofline": {"bound": "alu", "achieved": alu, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": alu / PEAK_VALU_TOPS, "traffic": None, "kernel": "decode_kernel (4 codes)"},
+        "roofline": {**dominant["roofline"], "code": dominant["name"],
+                     "what": "the dominant kernel (longest per-code launch of the mix)"},
     }
+    if not args.no_extras:
+        result["headline_c1008_sm_3.5dB"] = run_single_point(args, HEADLINE, quiet=True)
+    if not args.no_cpu_baseline:
+        oracle_build()
+        cores, model = host_cpu()
+        cpu_s, sample = 0.0, []
+        budget = args.cpu_seconds / len(items)
+        for it in items:
+            n_h = min(it["frames"], 1 << 14)
+            y_h = it["y"][:n_h].cpu().numpy()
+            fps, n1, dt, _ = oracle_rate(it["c"], y_h, it["sig_h"][:n_h], it["params"], it["seed"],
+                                         budget, cores)
+            cpu_s += it["frames"] / fps
+            sample.append(f"{it['name']}: {n1} frames in {dt:.1f} s")
+        result["cpu_baseline"] = {
+            "value": info_bits / cpu_s / 1e9, "unit": "Gbit/s", "cores": cores, "cpu_model": model,
+            "kind": "oracle",
+            "sample": "the first frames of every code of the mix (same inputs, parameters, noise keys); "
+                      + "; ".join(sample) + f"; whole-mix time extrapolated per code on {cores} host threads"}
     print(json.dumps(result), flush=True)
     for it in items:
         it["dc"].close()
@@ -292,7 +400,8 @@ def run_serve(args) -> int:
     import torch
 
     import paper_1402_2773_amd as ng
-    from synth import channel, codes
+    from paper_1402_2773_amd import sweep
+    from synth import codes
 
     names = [name for name, _, _ in MIX4]
     params = [ng.Params(**pr) for _, _, pr in MIX4]
@@ -309,8 +418,6 @@ def run_serve(args) -> int:
     ebn0 = rng.uniform(2.0, 5.0, n_req)
     rates = np.array([c.rate for c in cl])
     sig_req = (1.0 / np.sqrt(2.0 * rates[code_of] * 10.0 ** (ebn0 / 10.0))).astype(np.float32)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(4242)
 
     def serve(max_per_launch: int, per_stream: int, window: float):
         srv = ng.Server(dcs, params, pool, n_streams=4, max_requests_per_launch=max_per_launch,
@@ -332,7 +439,8 @@ def run_serve(args) -> int:
             starts = np.repeat(first - np.concatenate(([0], np.cumsum(frames)[:-1])), frames)
             slots = torch.from_numpy(starts + np.arange(tot)).cuda(non_blocking=True)
             sig = torch.from_numpy(np.repeat(sig_req[idx], frames)).cuda(non_blocking=True)
-            y = torch.randn((tot, cl[c].n), generator=gen, device="cuda").mul_(sig[:, None]).add_(1.0)
+            # the device channel, keyed by the arrival batch's first request
+            y = ng.channel(cl[c].n, tot, sig, seed=sweep.channel_seed(int(idx[0]) + 7919))
             srv.pools[c].y.index_copy_(0, slots, y)
             srv.pools[c].sigma.index_copy_(0, slots, sig)
 
@@ -423,9 +531,10 @@ def run_latency(args) -> int:
     import torch
 
     import paper_1402_2773_amd as ng
+    from paper_1402_2773_amd import sweep
     from synth import channel, codes
 
-    code_name, ebn0, params, _, _, desc = WORKLOADS[DEFAULT]
+    code_name, ebn0, params, _, _, desc = WORKLOADS[HEADLINE]
     code = codes.named_code(code_name)
     sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
     seed = 2000 + int(round(ebn0 * 10))
@@ -433,7 +542,7 @@ def run_latency(args) -> int:
     p = ng.Params(**params)
     rows = []
     for b in [1, 4, 16, 64, 256, 1024, 4096, 16384, 65536]:
-        y = channel.bpsk_awgn_device(b, code.n, sigma, seed=seed + b)
+        y = ng.channel(code.n, b, sigma, seed=sweep.channel_seed(seed + b))
         out = ng.alloc_outputs(dc, b, "cuda")
         reps = 200 if b <= 4096 else 50
         stream = torch.cuda.current_stream()
@@ -455,12 +564,120 @@ def run_latency(args) -> int:
         "metric": METRIC, "value": rows[-1]["info_gbps_at_p50"], "unit": "Gbit/s", "n_gpus": 1,
         "steps": len(rows), "warmup": 3, "ms_per_step": rows[-1]["p50_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic: seeded (3,6) LDPC code, all-zero codeword, BPSK-AWGN",
+        "data": "synthetic: seeded (3,6) LDPC code, all-zero codeword, BPSK-AWGN from the device channel",
         "config": {"workload": "latency", "description": desc + "; one launch per batch"},
         "latency_by_batch": rows,
     }
     print(json.dumps(result), flush=True)
     dc.close()
+    return 0
+
+
+def run_single_point(args, workload: str, quiet: bool = False) -> dict:
+    """One code at one Eb/N0 (WORKLOADS): K timed launches of the whole batch."""
+    import numpy as np
+    import torch
+
+    import paper_1402_2773_amd as ng
+    from paper_1402_2773_amd import sweep
+    from synth import channel, codes
+
+    code_name, ebn0, params, frames, yfmt, desc = WORKLOADS[workload]
+    if args.frames and not quiet:
+        frames = args.frames
+    code = codes.named_code(code_name)
+    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
+    seed = 2000 + int(round(ebn0 * 10))
+    dev_code = ng.Code.from_ldpc(code)
+    if args.shape and not quiet:
+        ng.ngdbf_code_set_shape(dev_code.handle, *[int(v) for v in args.shape.split(",")])
+    elif workload in WORKLOAD_SHAPES:
+        ng.ngdbf_code_set_shape(dev_code.handle, *WORKLOAD_SHAPES[workload])
+    y = ng.channel(code.n, frames, sigma, seed=sweep.channel_seed(seed), int8=yfmt == "i8")
+    p = ng.Params(**params)
+    out = ng.decode(dev_code, y, sigma, p, seed)  # allocate outputs once
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
+
+    ms_per_step, step_ms = timed_steps(torch, step, args.steps, args.warmup, stream)
+    st = stats_of(ng, dev_code, out, params["t_max"])
+    kernel_ms = float(np.mean(step_ms))
+    info_gbps = frames * code.k_info / (ms_per_step / 1e3) / 1e9
+    prof = (counter_profile(workload)
+            if frames == WORKLOADS[workload][3] and not (args.shape and not quiet) else None)
+    shape = list(ng.ngdbf_code_get_shape(dev_code.handle, p.c(ng.NGDBF_Y_F32)))
+    rf = roofline(code, frames, yfmt, kernel_ms, st["iterations"] * code.n,
+                  prof["instances"].get(code_name) if prof else None, False,
+                  f"decode_kernel<{shape[0]},{shape[1]},{0 if yfmt == 'f32' else 1},false,true,*>")
+    result = {
+        "metric": METRIC, "value": info_gbps, "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if yfmt == "f32" else "f32 (int8 y)",
+        "data": "synthetic: seeded regular LDPC code, all-zero codeword, BPSK-AWGN from the device channel",
+        "config": {"workload": workload, "description": desc, "code": code_name, "n": code.n, "m": code.m,
+                   "nnz": code.nnz, "frames": frames, "ebn0_db": ebn0, "sigma": sigma, "params": params,
+                   "y_format": yfmt, "seed": seed},
+        "edge_updates_per_s": st["iterations"] * code.nnz / (ms_per_step / 1e3),
+        "bit_iterations_per_s": st["iterations"] * code.n / (ms_per_step / 1e3),
+        "avg_iterations": st["avg_iterations"], "ber": st["ber"], "fer": st["fer"],
+        "unconverged_frames": st["unconverged_frames"], "launch_shape": shape,
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99)),
+                       "what": "one batch launch (all frames of the step)"},
+        "roofline": rf,
+    }
+    # the exact noise skip, counted in one more (untimed) decode: pairs of bits
+    # whose decision the radius bound fixed without a Box-Muller transform
+    counted = (params.get("variant", 0) == 0 and params.get("quant_bits", 0) == 0
+               and params.get("noise_reuse", 0) == 0)
+    if counted and not args.no_draw_stats:
+        counters = torch.zeros(2, dtype=torch.int64, device="cuda")
+        ng.ngdbf_code_set_stats(dev_code.handle, counters)
+        ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ng.ngdbf_code_set_stats(dev_code.handle, None)
+        evaluated, transformed = (int(v) for v in counters.cpu().tolist())
+        result["gaussian_draws"] = {
+            "defined": 2 * evaluated, "transformed": 2 * transformed,
+            "skipped_frac": 1.0 - transformed / evaluated if evaluated else None,
+            "what": "draws the method defines (one per bit and round) and those the "
+                    "kernel computed: the rest could not change a decision"}
+    if not args.no_cpu_baseline and not quiet:
+        y_host = y[: min(frames, 1 << 16)].cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline(code, y_host, sigma, params, seed, args.cpu_seconds)
+    dev_code.close()
+    del y, out
+    return result
+
+
+def run_issue_rates(args) -> int:
+    """Clocks a wave64 vector-ALU instruction of each class holds its SIMD:
+    the library's issue probe (long unrolled chains of one class) at eight
+    waves per SIMD, timed with HIP events, at the 2.4 GHz clock."""
+    import torch
+
+    import paper_1402_2773_amd as ng
+
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks, iters = cus * 8, 2000
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    names = ["int32 (v_xad_u32)", "int64 product + xor (v_mad_u64_u32, v_xor_b32)", "fp32 fma",
+             "fp32 mul", "fp32 sqrt (transcendental)"]
+    per_step = [1, 2, 1, 1, 1]
+    rows = []
+    for kind in range(5):
+        def one(kind=kind):
+            ng.ngdbf_issue_probe(kind, blocks, iters, out, stream)
+        _, ms = timed_steps(torch, one, 3, 1, stream)
+        steps_per_simd = blocks * 4 * iters * 16 * 8 / (cus * 4.0)
+        cyc = min(ms) * 1e-3 * 2.4e9 / steps_per_simd / per_step[kind]
+        rows.append({"class": names[kind], "ms": min(ms), "clocks_per_wave64_instruction": cyc})
+        print(f"# {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "issue-rates", "cus": cus, "clock_ghz_assumed": 2.4,
+                      "waves_per_simd": 8, "rows": rows}), flush=True)
     return 0
 
 
@@ -470,11 +687,13 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency"])
+                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency", "issue-rates"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
     ap.add_argument("--shape", default="", help="fix the launch shape: waves,quads,frames_per_block")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="mix4: skip the single-code headline point (profiling runs)")
     ap.add_argument("--no-draw-stats", action="store_true",
                     help="skip the extra decode that counts the Gaussian draws (profiling runs)")
     ap.add_argument("--mix-autotune", action="store_true", help="mix4: autotune each code first")
@@ -494,11 +713,7 @@ def main() -> int:
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
-
-    import paper_1402_2773_amd as ng
-    from synth import channel, codes
 
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -515,112 +730,9 @@ def main() -> int:
         return run_serve(args)
     if args.workload == "latency":
         return run_latency(args)
-    code_name, ebn0, params, frames, yfmt, desc = WORKLOADS[args.workload]
-    if args.frames:
-        frames = args.frames
-    code = codes.named_code(code_name)
-    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
-    seed = 2000 + int(round(ebn0 * 10))
-    dev_code = ng.Code.from_ldpc(code)
-    if args.shape:
-        ng.ngdbf_code_set_shape(dev_code.handle, *[int(v) for v in args.shape.split(",")])
-    elif args.workload in WORKLOAD_SHAPES:
-        ng.ngdbf_code_set_shape(dev_code.handle, *WORKLOAD_SHAPES[args.workload])
-    y = channel.bpsk_awgn_device(frames, code.n, sigma, seed=seed)
-    if yfmt == "i8":
-        y = channel.quantize_int8(y)
-    p = ng.Params(**params)
-    out = ng.decode(dev_code, y, sigma, p, seed)  # allocate outputs once
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        ng.decode(dev_code, y, sigma, p, seed, out=out)
-    torch.cuda.synchronize()
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in evs:
-        e0.record(stream)
-        ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
-
-    iters = out.iters.to(torch.int64)
-    bit_iters = float(iters.sum().item()) * code.n
-    edge_updates = float(iters.sum().item()) * code.nnz
-    errs = torch.from_numpy(np.unpackbits(out.bits.cpu().numpy(), axis=1, bitorder="little")[:, :code.n])
-    bit_err = int(errs.sum().item())
-    frame_err = int((errs.sum(dim=1) > 0).sum().item())
-    kernel_s = float(np.mean(step_ms)) / 1e3
-    ms_per_step = wall / args.steps * 1e3
-    info_gbps = frames * code.k_info / (ms_per_step / 1e3) / 1e9
-
-    alu = algorithmic_valu_ops(code, bit_iters, params, frames) / kernel_s / 1e12
-    alg_bytes = frames * hbm_bytes_per_frame(code, yfmt)
-    hbm = alg_bytes / kernel_s / 1e9
-    tr = (measured_traffic(args.workload)
-          if frames == WORKLOADS[args.workload][3] and not args.shape else None)
-    result = {
-        "metric": METRIC,
-        "value": info_gbps,
-        "unit": "Gbit/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if yfmt == "f32" else "f32 (int8 y)",
-        "data": "synthetic: seeded (3,6)/(6,32) regular LDPC codes, all-zero codeword, BPSK-AWGN",
-        "config": {"workload": args.workload, "description": desc, "code": code_name,
-                   "n": code.n, "m": code.m, "nnz": code.nnz, "frames": frames,
-                   "ebn0_db": ebn0, "sigma": sigma, "params": params, "y_format": yfmt,
-                   "seed": seed},
-        "edge_updates_per_s": edge_updates / (ms_per_step / 1e3),
-        "bit_iterations_per_s": bit_iters / (ms_per_step / 1e3),
-        "avg_iterations": float(iters.double().mean().item()),
-        "ber": bit_err / (frames * code.n),
-        "fer": frame_err / frames,
-        "unconverged_frames": int((out.converged == 0).sum().item()),
-        "launch_shape": list(ng.ngdbf_code_get_shape(dev_code.handle, p.c(ng.NGDBF_Y_F32))),
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99)),
-                       "what": "one batch launch (all frames of the step)"},
-        "roofline": {"bound": "alu", "achieved": alu, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": alu / PEAK_VALU_TOPS,
-                     "traffic": tr["traffic_bytes_per_launch"] if tr else None,
-                     "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes": alg_bytes,
-                     "kernel": "decode_kernel", "kernel_ms": kernel_s * 1e3,
-                     "hbm_achieved_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS},
-    }
-    # the exact noise skip, counted in one more (untimed) decode: pairs of bits
-    # whose decision the radius bound fixed without a Box-Muller transform
-    counted = (params.get("variant", 0) == 0 and params.get("quant_bits", 0) == 0
-               and params.get("noise_reuse", 0) == 0)
-    if counted and not args.no_draw_stats:
-        counters = torch.zeros(2, dtype=torch.int64, device="cuda")
-        ng.ngdbf_code_set_stats(dev_code.handle, counters)
-        ng.decode(dev_code, y, sigma, p, seed, out=out, stream=stream)
-        torch.cuda.synchronize()
-        ng.ngdbf_code_set_stats(dev_code.handle, None)
-        evaluated, transformed = (int(v) for v in counters.cpu().tolist())
-        result["gaussian_draws"] = {
-            "defined": 2 * evaluated, "transformed": 2 * transformed,
-            "skipped_frac": 1.0 - transformed / evaluated if evaluated else None,
-            "what": "draws the method defines (one per bit and round) and those the "
-                    "kernel computed: the rest could not change a decision"}
-    if not args.no_cpu_baseline:
-        y_host = y[: min(frames, 1 << 16)].cpu().numpy()
-        result["cpu_baseline"] = cpu_baseline(code, y_host, sigma, params, seed, args.cpu_seconds)
-    print(json.dumps(result), flush=True)
-    dev_code.close()
+    if args.workload == "issue-rates":
+        return run_issue_rates(args)
+    print(json.dumps(run_single_point(args, args.workload)), flush=True)
     return 0
 
 

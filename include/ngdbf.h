@@ -437,6 +437,70 @@ ngdbf_status ngdbf_objective(const ngdbf_code *code, const void *y, int32_t y_fo
                     int64_t n_frames, float ymax, const uint8_t *bits, int64_t *out,
                     void *stream);
 
+/*
+ * ngdbf_channel -- the synthetic channel of Sec. III-A on the device: BPSK
+ * symbols c_hat_k = 1 - 2 c_k plus Gaussian noise of std sigma,
+ *   y_k = fmaf(sigma_f, z_k, c_hat_k),
+ * with z_k the standard-normal draw of bit k that the decoder's generator
+ * gives under the iteration word 0xFFFFFFFE (Philox4x32-10 counter (k >> 2,
+ * 0xFFFFFFFE, frame lo, frame hi), key = seed, Box-Muller as for the
+ * perturbations; no decoding round and not the noise-reuse stream uses that
+ * word), frame = frame_base + f.  A CPU implementation can regenerate every
+ * sample bit for bit.
+ *   n, n_frames : code length (1 .. 65535) and frames (>= 0).
+ *   sigma       : dev float32 [n_frames] or NULL (sigma_scalar, finite >= 0).
+ *   codewords   : dev uint8 [n_frames][ceil(n/8)] sent bits c_k, LSB first,
+ *                 or NULL for the all-zero codeword.
+ *   y_format    : NGDBF_Y_F32 (y float32 [n_frames][n]) or NGDBF_Y_I8 (int8
+ *                 codes y_q = clamp(rint(16 y), -127, 127), ties to even).
+ *   y           : dev output, owned by the caller.
+ * Errors: NGDBF_EINVAL, NGDBF_EDEVICE.
+ */
+ngdbf_status ngdbf_channel(int32_t n, int64_t n_frames, const float *sigma, float sigma_scalar,
+                           uint64_t seed, uint64_t frame_base, const uint8_t *codewords,
+                           int32_t y_format, void *y, void *stream);
+
+/*
+ * ngdbf_frame_stats -- Monte Carlo counters of decoded frames (the BER, FER
+ * and iteration statistics of Sec. IV-A/B), accumulated into out (the caller
+ * zeroes it; several calls add up):
+ *   out[0] bit errors sum_f e_f, with e_f the bits of the decision that
+ *          differ from the sent word (all of the frame's n code bits);
+ *   out[1] sum_f e_f^2 (for bit-error intervals clustered by frame);
+ *   out[2] frame errors (e_f > 0);  out[3] undetected errors (e_f > 0 on a
+ *          frame whose stop test ended decoding; 0 if converged is NULL);
+ *   out[4] sum of iteration counts;  out[5] unconverged frames (0 if
+ *          converged is NULL);  out[6 + t] frames that took t rounds,
+ *          t = 0 .. t_max (counts above t_max land in the last bin).
+ *   bits      : dev [n_frames][ceil(n/8)] decisions (ngdbf_decode's out_bits).
+ *   codewords : dev sent bits in the same layout, or NULL (all-zero word).
+ *   iters     : dev int32 [n_frames]; converged: dev uint8 [n_frames] or NULL.
+ *   out       : dev int64 [7 + t_max], t_max in [0, 65535].
+ * Errors: NGDBF_EINVAL, NGDBF_EDEVICE.
+ */
+ngdbf_status ngdbf_frame_stats(int32_t n, int64_t n_frames, const uint8_t *bits,
+                               const uint8_t *codewords, const int32_t *iters,
+                               const uint8_t *converged, int32_t t_max, int64_t *out,
+                               void *stream);
+
+/*
+ * ngdbf_issue_probe -- instrumentation: a kernel of long unrolled chains of
+ * one vector-ALU instruction class, for measuring how many clocks a wave64
+ * instruction of that class holds a SIMD (the decoder is bound by vector-ALU
+ * issue; the benchmark weights each class's hardware counter by this time).
+ *   kind   : 0 32-bit integer (v_xad_u32), 1 64-bit product plus xor
+ *            (v_mad_u64_u32, v_xor_b32), 2 binary32 fma, 3 binary32 multiply,
+ *            4 transcendental (v_sqrt_f32); every chain step is one
+ *            instruction (kind 1: two).
+ *   blocks : workgroups of 256 threads; iters >= 1 outer iterations of 16 x 8
+ *            chain steps per thread.
+ *   out    : dev uint32 [blocks * 256], receives a value per thread.
+ * Errors: NGDBF_EINVAL (kind, sizes or NULL out), NGDBF_EDEVICE.  Does not set
+ * ngdbf_last_error.
+ */
+ngdbf_status ngdbf_issue_probe(int32_t kind, int32_t blocks, int32_t iters, uint32_t *out,
+                               void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *ngdbf_last_error(void);
 

@@ -110,6 +110,9 @@ def lib():
                                           ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                           P, P]
         L.ngdbf_ref_objective.restype = ctypes.c_int
+        L.ngdbf_ref_channel.argtypes = [ctypes.c_int32, ctypes.c_int64, P, ctypes.c_float,
+                                        ctypes.c_uint64, ctypes.c_uint64, P, ctypes.c_int32, P]
+        L.ngdbf_ref_channel.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -202,6 +205,26 @@ def objective(code, y: np.ndarray, ymax: float, bits: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return out
+
+
+def channel(n: int, n_frames: int, sigma, seed: int, frame_base: int = 0,
+            codewords: Optional[np.ndarray] = None, int8: bool = False) -> np.ndarray:
+    """Received samples of the synthetic channel (Sec. III-A), [F, n] float32
+    (or int8 codes y_q = clamp(rint(16 y), -127, 127) with int8=True)."""
+    sig_arr, sig_scalar = None, 0.0
+    if np.ndim(sigma) == 0:
+        sig_scalar = float(np.float32(sigma))
+    else:
+        sig_arr = np.ascontiguousarray(sigma, dtype=np.float32)
+        if sig_arr.shape != (n_frames,):
+            raise ValueError("sigma must be a scalar or one value per frame")
+    cw = None if codewords is None else np.ascontiguousarray(codewords, dtype=np.uint8)
+    y = np.zeros((n_frames, n), dtype=np.int8 if int8 else np.float32)
+    rc = lib().ngdbf_ref_channel(n, n_frames, _ptr(sig_arr), sig_scalar, seed, frame_base,
+                                 _ptr(cw), 1 if int8 else 0, _ptr(y))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return y
 
 
 @dataclasses.dataclass

@@ -325,6 +325,43 @@ float ngdbf_ref_reuse_sample(uint64_t seed, uint64_t frame, int32_t n,
 }
 
 /* ------------------------------------------------------------------ */
+/* Channel of Sec. III-A: y = c_hat + z, z ~ N(0, sigma^2).           */
+/* ------------------------------------------------------------------ */
+
+/* The synthetic channel: BPSK symbol c_hat_k = 1 - 2 c_k (all-zero codeword
+ * when no codeword is given) plus sigma z_k, formed as fmaf(sigma, z_k,
+ * c_hat_k), with z_k the standard-normal draw of bit k under the iteration
+ * word 0xFFFFFFFE (a value no decoding round and not the noise-reuse stream
+ * takes) for the frame's index, keyed by the channel's own seed.  int8
+ * storage: y_q = clamp(rint(16 y), -127, 127), ties to even. */
+int ngdbf_ref_channel(int32_t n, int64_t n_frames, const float *sigma,
+                      float sigma_scalar, uint64_t seed, uint64_t frame_base,
+                      const uint8_t *codewords, int32_t y_format, void *y) {
+    if (n < 1 || n_frames < 0 || (y_format != 0 && y_format != 1)) return -1;
+    if (n_frames > 0 && !y) return -1;
+    int32_t nb = (n + 7) / 8;
+    for (int64_t f = 0; f < n_frames; ++f) {
+        float sg = sigma ? sigma[f] : sigma_scalar;
+        uint64_t frame = frame_base + (uint64_t)f;
+        for (int32_t k = 0; k < n; ++k) {
+            float z4[4];
+            ngdbf_ref_noise_quad(seed, frame, 0xFFFFFFFEu, (uint32_t)k >> 2, z4);
+            int c = codewords ? (codewords[(size_t)f * nb + (k >> 3)] >> (k & 7)) & 1 : 0;
+            float v = fmaf(sg, z4[k & 3], c ? -1.0f : 1.0f);
+            if (y_format == 0) {
+                ((float *)y)[(size_t)f * n + k] = v;
+            } else {
+                float q = rintf(16.0f * v);          /* 16 v is exact; rint: ties to even */
+                if (!(q >= -127.0f)) q = -127.0f;    /* a NaN sample saturates low */
+                if (q > 127.0f) q = 127.0f;
+                ((int8_t *)y)[(size_t)f * n + k] = (int8_t)q;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Objective function (Sec. III-B) in exact fixed point.              */
 /* ------------------------------------------------------------------ */
 

@@ -117,6 +117,17 @@ int32_t ngdbf_ref_threshold_events(float theta, float lambda, float ymax,
 float ngdbf_ref_reuse_sample(uint64_t seed, uint64_t frame, int32_t n,
                              uint32_t t, int32_t k);
 
+/* The synthetic channel of Sec. III-A: y_k = fmaf(sigma_f, z_k, 1 - 2 c_k)
+ * for frame f (noise index frame_base + f), with z_k the standard-normal draw
+ * of bit k under iteration word 0xFFFFFFFE and key `seed`.
+ *   sigma: per-frame std (may be NULL: sigma_scalar for all frames).
+ *   codewords: frames x ceil(n/8) sent bits c_k, LSB first (NULL: all zero).
+ *   y_format 0: float32 y [F][n]; 1: int8 y_q = clamp(rint(16 y), -127, 127).
+ * Returns 0, or -1 on an invalid argument. */
+int ngdbf_ref_channel(int32_t n, int64_t n_frames, const float *sigma,
+                      float sigma_scalar, uint64_t seed, uint64_t frame_base,
+                      const uint8_t *codewords, int32_t y_format, void *y);
+
 /* GDBF objective of Sec. III-B, f(x) = sum_k x_k y_k + sum_i s_i, in fixed
  * point: F = sum_k x_k Y_k + 2^20 sum_i s_i with Y_k = rint(2^20 y_k) (y_k
  * saturated at ymax as in decoding, clamped to +-2^40; NaN counts 0), exact

@@ -28,7 +28,8 @@ ABI_FUNCTIONS = ("ngdbf_create_code", "ngdbf_destroy_code", "ngdbf_code_info", "
                  "ngdbf_decode_segments", "ngdbf_server_create", "ngdbf_server_destroy",
                  "ngdbf_server_pools", "ngdbf_server_admit", "ngdbf_server_commit",
                  "ngdbf_server_pump", "ngdbf_server_poll", "ngdbf_server_release",
-                 "ngdbf_objective", "ngdbf_last_error")
+                 "ngdbf_objective", "ngdbf_channel", "ngdbf_frame_stats", "ngdbf_issue_probe",
+                 "ngdbf_last_error")
 
 
 NGDBF_MULTI, NGDBF_SINGLE, NGDBF_MODE_SWITCH = 0, 1, 2
@@ -129,6 +130,9 @@ def lib() -> ctypes.CDLL:
         L.ngdbf_server_poll.argtypes = [P, I32, P, P]
         L.ngdbf_server_release.argtypes = [P, I32, P]
         L.ngdbf_objective.argtypes = [P, P, I32, I64, F, P, P, P]
+        L.ngdbf_issue_probe.argtypes = [I32, I32, I32, P, P]
+        L.ngdbf_channel.argtypes = [I32, I64, P, F, U64, U64, P, I32, P, P]
+        L.ngdbf_frame_stats.argtypes = [I32, I64, P, P, P, P, I32, P, P]
         L.ngdbf_last_error.argtypes = []
         L.ngdbf_last_error.restype = ctypes.c_char_p
         for name in ABI_FUNCTIONS:
@@ -336,6 +340,24 @@ def ngdbf_objective(code, y, y_format: int, n_frames: int, ymax: float, bits, ou
                                  _addr(out), _stream(stream)))
 
 
+def ngdbf_channel(n: int, n_frames: int, sigma, sigma_scalar: float, seed: int, frame_base: int,
+                  codewords, y_format: int, y, stream) -> None:
+    _check(lib().ngdbf_channel(n, n_frames, _addr(sigma), sigma_scalar, seed, frame_base,
+                               _addr(codewords), y_format, _addr(y), _stream(stream)))
+
+
+def ngdbf_frame_stats(n: int, n_frames: int, bits, codewords, iters, converged, t_max: int, out,
+                      stream) -> None:
+    _check(lib().ngdbf_frame_stats(n, n_frames, _addr(bits), _addr(codewords), _addr(iters),
+                                   _addr(converged), t_max, _addr(out), _stream(stream)))
+
+
+def ngdbf_issue_probe(kind: int, blocks: int, iters: int, out, stream) -> None:
+    status = lib().ngdbf_issue_probe(kind, blocks, iters, _addr(out), _stream(stream))
+    if status != 0:
+        raise NgdbfError(status, "issue probe rejected its arguments or failed to launch")
+
+
 def ngdbf_last_error() -> str:
     return lib().ngdbf_last_error().decode()
 
@@ -517,6 +539,33 @@ def _wrap(addr: int, shape, dtype, device):
 
     typestr = {torch.uint8: "|u1", torch.int32: "<i4", torch.float32: "<f4"}[dtype]
     return torch.as_tensor(_DeviceBuffer(addr, shape, typestr), device=device)
+
+
+def channel(n: int, n_frames: int, sigma, seed: int, frame_base: int = 0, codewords=None,
+            int8: bool = False, device="cuda", stream=None, out=None):
+    """Received samples of the synthetic channel (Sec. III-A) generated on the
+    device: torch [F, n] float32 (int8 codes with int8=True).  sigma: a float
+    or a device float32 [F] tensor."""
+    import torch
+
+    if out is None:
+        out = torch.empty((n_frames, n), dtype=torch.int8 if int8 else torch.float32, device=device)
+    sig_t, sig_s = (sigma, 0.0) if isinstance(sigma, torch.Tensor) else (None, float(sigma))
+    ngdbf_channel(n, n_frames, sig_t, sig_s, seed, frame_base, codewords,
+                  NGDBF_Y_I8 if int8 else NGDBF_Y_F32, out, stream)
+    return out
+
+
+def frame_stats(code: Code, out: Outputs, t_max: int, codewords=None, stream=None, acc=None):
+    """int64 [7 + t_max] device counters of decoded frames (ngdbf_frame_stats),
+    added to acc if given."""
+    import torch
+
+    if acc is None:
+        acc = torch.zeros(7 + t_max, dtype=torch.int64, device=out.bits.device)
+    ngdbf_frame_stats(code.n, out.bits.shape[0], out.bits, codewords, out.iters, out.converged,
+                      t_max, acc, stream)
+    return acc
 
 
 def objective(code: Code, y, ymax: float, bits, stream=None):

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libngdbf.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
            for f in ("decode.hip", "decode_ext_multi.hip", "decode_ext_single.hip",
-                     "decode_ext_switch.hip", "decode_ext_packed.hip", "server.cpp")]
+                     "decode_ext_switch.hip", "decode_ext_packed.hip", "channel.hip", "probe.hip", "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NGDBF_ARCH", "gfx950")
 

@@ -92,39 +92,45 @@ def wilson(k: int, n: int, z: float = 1.96):
     return (max(0.0, c - h), min(1.0, c + h))
 
 
-def _stats(torch, code, out, frames: int):
-    """BER, FER, its interval, undetected errors and iteration percentiles."""
-    errs = _errors(torch, out.bits, code.n)
-    fe = int((errs > 0).sum().item())
-    und = int(((errs > 0) & (out.converged == 1)).sum().item())
-    it = out.iters.double()
-    q = torch.quantile(it[: min(frames, 1 << 24)], torch.tensor([0.5, 0.9, 0.99], dtype=torch.float64,
-                                                                 device=it.device))
-    return dict(ber=float(errs.sum().item()) / (frames * code.n), fer=fe / frames,
-                fer_ci95=wilson(fe, frames), undetected=und,
-                avg_iterations=float(it.mean().item()),
-                unconverged=int((out.converged == 0).sum().item()),
-                iter_percentiles=tuple([float(v) for v in q.tolist()] + [float(it.max().item())]))
+def _stats(torch, code, out, frames: int, t_max: int, dev_code=None):
+    """BER, FER, its interval, undetected errors and iteration percentiles,
+    from the device counters of ngdbf_frame_stats (errors against the
+    all-zero codeword the synthetic channel sends)."""
+    acc = ng.frame_stats(dev_code, out, t_max).cpu().tolist()
+    return _from_counters(acc, frames, code.n, t_max)
 
 
-def _errors(torch, bits, n):
-    """Bit errors per frame against the all-zero codeword (popcount of the
-    decoded bits, padding bits are zero)."""
-    table = torch.tensor([bin(i).count("1") for i in range(256)], dtype=torch.int32,
-                         device=bits.device)
-    return table[bits.long()].sum(dim=1)
+def _from_counters(acc, frames: int, n: int, t_max: int):
+    hist = acc[6:6 + t_max + 1]
+    cum, pct, targets = 0, [], [0.5, 0.9, 0.99]
+    for t, h in enumerate(hist):
+        cum += h
+        while targets and cum >= targets[0] * frames:
+            pct.append(float(t))
+            targets.pop(0)
+    top = max((t for t, h in enumerate(hist) if h), default=0)
+    fe = int(acc[2])
+    return dict(ber=acc[0] / (frames * n), fer=fe / frames, fer_ci95=wilson(fe, frames),
+                undetected=int(acc[3]), avg_iterations=acc[4] / frames, unconverged=int(acc[5]),
+                iter_percentiles=tuple(pct + [float(top)]))
 
 
-def _channel(code, ebn0: float, frames: int, seed: int, y_format: str):
-    from synth import channel
-
-    sigma = float(channel.sigma_from_ebn0(ebn0, code.rate))
-    y = channel.bpsk_awgn_device(frames, code.n, sigma, seed=seed)
-    if y_format == "i8":
-        y = channel.quantize_int8(y)
+def _channel(code, ebn0: float, frames: int, seed: int, y_format: str, frame_base: int = 0):
+    """Received frames from the device channel (ngdbf_channel), keyed by the
+    channel seed and the frames' global indices."""
     import numpy as np
 
-    return y, float(np.float32(sigma))
+    from synth import channel
+
+    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, code.rate)))
+    y = ng.channel(code.n, frames, sigma, seed=channel_seed(seed), frame_base=frame_base,
+                   int8=y_format == "i8")
+    return y, sigma
+
+
+def channel_seed(seed: int) -> int:
+    """The channel's Philox key for a run whose decoder key is seed."""
+    return (seed * 0x9E3779B97F4A7C15 + 0x632BE59BD9B4E019) & 0xFFFFFFFFFFFFFFFF
 
 
 def run_point(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
@@ -145,7 +151,7 @@ def run_point(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
     ms = e0.elapsed_time(e1)
     return Point(code=code.name, ebn0=ebn0, params=params, frames=frames, y_format=y_format,
                  kernel_ms=ms, info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed,
-                 **_stats(torch, code, out, frames))
+                 **_stats(torch, code, out, frames, params["t_max"], dev_code))
 
 
 def run_point_chunked(code, dev_code, ebn0: float, params: Dict, frames: int, seed: int,
@@ -163,7 +169,8 @@ def run_point_chunked(code, dev_code, ebn0: float, params: Dict, frames: int, se
 
     n_chunks = (frames + chunk - 1) // chunk
     key = {"code": code.name, "code_digest": code.digest(), "ebn0": ebn0, "params": params,
-           "frames": frames, "chunk": chunk, "seed": seed, "y_format": y_format}
+           "frames": frames, "chunk": chunk, "seed": seed, "y_format": y_format,
+           "channel": "device Philox, iteration word 0xFFFFFFFE"}
     state = {"key": key, "next_chunk": 0, "bit_errors": 0, "frame_errors": 0, "undetected": 0,
              "unconverged": 0, "iterations": 0, "iteration_histogram": [0] * (params["t_max"] + 1)}
     if os.path.exists(state_path):
@@ -180,19 +187,17 @@ def run_point_chunked(code, dev_code, ebn0: float, params: Dict, frames: int, se
             return None
         c = state["next_chunk"]
         fc = min(chunk, frames - c * chunk)
-        y = channel.bpsk_awgn_device(fc, code.n, sigma, seed=seed * 1000003 + c)
-        if y_format == "i8":
-            y = channel.quantize_int8(y)
+        y = ng.channel(code.n, fc, sigma, seed=channel_seed(seed), frame_base=c * chunk,
+                       int8=y_format == "i8")
         out = ng.decode(dev_code, y, sigma, p, seed, frame_base=c * chunk)
-        errs = _errors(torch, out.bits, code.n)
-        hist = torch.bincount(out.iters.long(), minlength=params["t_max"] + 1)
-        state["bit_errors"] += int(errs.sum().item())
-        state["frame_errors"] += int((errs > 0).sum().item())
-        state["undetected"] += int(((errs > 0) & (out.converged == 1)).sum().item())
-        state["unconverged"] += int((out.converged == 0).sum().item())
-        state["iterations"] += int(out.iters.long().sum().item())
+        acc = ng.frame_stats(dev_code, out, params["t_max"]).cpu().tolist()
+        state["bit_errors"] += int(acc[0])
+        state["frame_errors"] += int(acc[2])
+        state["undetected"] += int(acc[3])
+        state["unconverged"] += int(acc[5])
+        state["iterations"] += int(acc[4])
         state["iteration_histogram"] = [a + int(b) for a, b in
-                                        zip(state["iteration_histogram"], hist.tolist())]
+                                        zip(state["iteration_histogram"], acc[6:])]
         state["next_chunk"] = c + 1
         tmp = state_path + ".tmp"
         with open(tmp, "w") as f:
@@ -227,7 +232,7 @@ def run_grid(code, dev_code, ebn0: float, param_list: Sequence[Dict], frames: in
         pts.append(Point(code=code.name, ebn0=ebn0, params=dict(pr), frames=frames,
                          y_format=y_format, kernel_ms=ms,
                          info_gbps=frames * code.k_info / (ms / 1e3) / 1e9, seed=seed,
-                         **_stats(torch, code, out, frames)))
+                         **_stats(torch, code, out, frames, pr["t_max"], dev_code)))
     return pts
 
 
@@ -285,12 +290,11 @@ def convergence_error(code, dev_code, ebn0: float, params: Dict, frames: int, se
     f_out = ng.objective(dev_code, y, params["ymax"], out.bits)
     f_max = ng.objective(dev_code, y, params["ymax"], torch.zeros_like(out.bits))
     torch.cuda.synchronize()
-    gap = (f_out - f_max).double() / 2.0 ** 20
-    errs = _errors(torch, out.bits, code.n)
+    gap = (f_out - f_max).cpu().numpy().astype("float64") / 2.0 ** 20
+    acc = ng.frame_stats(dev_code, out, params["t_max"]).cpu().tolist()
     return {"code": code.name, "ebn0": ebn0, "frames": frames, "params": params,
-            "eps": float(gap.mean().item()), "eps_std": float(gap.std().item()) if frames > 1 else 0.0,
-            "fer": float((errs > 0).double().mean().item()),
-            "avg_iterations": float(out.iters.double().mean().item()), "seed": seed}
+            "eps": float(gap.mean()), "eps_std": float(gap.std(ddof=1)) if frames > 1 else 0.0,
+            "fer": acc[2] / frames, "avg_iterations": acc[4] / frames, "seed": seed}
 
 
 def _range(spec: str) -> List[float]:

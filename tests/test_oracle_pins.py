@@ -396,3 +396,48 @@ def test_binary64_decoder_with_adaptation_and_smoothing(oracle_lib, ebn0, lam, f
     unconv = same & (a.converged == 0)
     assert unconv.sum() >= 3, "some frames must reach T (smoothing in use)"
     assert (a.bits[unconv] == b.bits[unconv]).all(axis=1).mean() > 0.9
+
+
+# ------------------------------------------------------------- the synthetic channel
+
+def test_channel_hard_decision_error_rate_closed_form(oracle_lib):
+    """Sec. III-A with sigma = 0.668 (3.50 dB for a rate-1/2 code, the paper's
+    Sec. VII example): the fraction of samples below zero is Phi(-1/sigma) =
+    0.0672 within a 99.9% binomial interval on 2.0e6 independent samples."""
+    sig = np.float32(0.668)
+    y = oracle.channel(1000, 2000, sig, seed=31)
+    k, n = int((y < 0).sum()), y.size
+    p = stats.norm.cdf(-1.0 / float(sig))
+    assert abs(p - 0.0672) < 5e-5
+    assert abs(k / n - p) < 3.29 * math.sqrt(p * (1 - p) / n)
+
+
+def test_channel_noise_moments_and_normality(oracle_lib):
+    sig = np.float32(0.8)
+    y = oracle.channel(512, 400, sig, seed=32).astype(np.float64)
+    z = (y - 1.0) / float(sig)
+    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / z.size)
+    assert stats.kstest(z.ravel()[:20000], "norm").pvalue > 1e-3
+
+
+def test_channel_special_cases(oracle_lib):
+    """sigma = 0 gives the BPSK symbols exactly (c_hat = 1 - 2c); the frame
+    index keys the noise (a shifted frame_base reproduces the same frames);
+    int8 storage is clamp(rint(16 y), -127, 127) of the float32 samples."""
+    rng = np.random.Generator(np.random.PCG64(33))
+    cw = rng.integers(0, 256, size=(6, 13), dtype=np.uint8)
+    y0 = oracle.channel(100, 6, 0.0, seed=34, codewords=cw)
+    bits = oracle.unpack_bits(cw, 100)
+    assert (y0 == (1.0 - 2.0 * bits).astype(np.float32)).all()
+    sig = channel.frame_sigmas(9, 2.0, 5.0, 0.5, seed=35)
+    a = oracle.channel(100, 9, sig, seed=36, frame_base=1000)
+    b = oracle.channel(100, 9 + 4, np.concatenate([np.ones(4, np.float32), sig]), seed=36, frame_base=996)
+    assert (a == b[4:]).all()
+    q = oracle.channel(100, 9, sig, seed=36, frame_base=1000, int8=True)
+    ref = np.clip(np.rint(a.astype(np.float64) * 16.0), -127, 127).astype(np.int8)
+    assert (q == ref).all()
+    # the channel's draws are not the decoder's round-0 draws of the same frame
+    z0 = oracle.noise_block(36, 1000, 0, 0, 25)
+    zc = (a[0].astype(np.float64) - 1.0) / float(sig[0])
+    assert abs(np.corrcoef(z0, zc)[0, 1]) < 0.5
