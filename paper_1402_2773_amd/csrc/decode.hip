@@ -351,28 +351,31 @@ int packed_table_words(const Layout &L) { return L.packed ? ((L.t_max + 2) / 2 +
 
 int list_words(const Layout &L) {
   if (!L.lists) return 0;
-  return L.lazy ? ngdbf::kEntryWordsLazy * ngdbf::kListCapLazy : ngdbf::kEntryWords * ngdbf::kListCap;
+  return L.lazy ? ngdbf::kEntryWordsLazy * ngdbf::kListCapLazy + ngdbf::kDecisionWords
+                : ngdbf::kEntryWords * ngdbf::kListCap;
 }
 
 // Word offsets within one frame slot: s | u | x | flips | count | 2 event
-// counters | toggles | events [| flip counts] [| reductions | stream]; even,
+// counters | 2 count changes | toggles | events [| flip counts] [| reductions
+// | stream]; even,
 // so that 64-bit LDS atomics are aligned.
 struct SlotPlan {
   int red_off = 0, stream_off = 0, clear_words = 0, slot_words = 0, fc_off = 0;
 };
 
-// Check-toggle events a frame lists per round for the parallel u update: one
-// per check (a round toggles each check at most once), within the exact range
-// of the kernel's division by d_c; irregular codes apply their toggles
-// directly and list none.
-int event_cap(const ngdbf_code *c) {
+// Check-toggle events a frame lists per round for the parallel u update: up
+// to one per check (a round toggles each check at most once), 256 per wave of
+// the frame (events past the cap are applied by their owners, slower but
+// alike), within the exact range of the kernel's division by d_c; irregular
+// codes apply their toggles directly and list none.
+int event_cap(const ngdbf_code *c, int wpf) {
   if (!c->dc) return 0;
-  return std::min(c->m, std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
+  return std::min(std::min(c->m, 256 * wpf), std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
 }
 
-SlotPlan slot_plan(const ngdbf_code *c, const Layout &L) {
-  int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 3 +
-          (c->m + 31) / 32 + event_cap(c);
+SlotPlan slot_plan(const ngdbf_code *c, const Layout &L, int wpf) {
+  int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 5 +
+          (c->m + 31) / 32 + event_cap(c, wpf);
   SlotPlan p;
   if (L.ext) {
     w = (w + 1) & ~1;
@@ -409,7 +412,7 @@ int slots_offset(const ngdbf_code *c, const Layout &L, const Shape &sh) {
 }
 
 size_t lds_bytes(const ngdbf_code *c, const Shape &sh, const Layout &L) {
-  return ((size_t)slots_offset(c, L, sh) + (size_t)sh.fpb * slot_plan(c, L).slot_words +
+  return ((size_t)slots_offset(c, L, sh) + (size_t)sh.fpb * slot_plan(c, L, sh.wpf).slot_words +
           (size_t)(sh.block() / 64) * list_words(L)) * 4;
 }
 
@@ -613,9 +616,9 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.sw_words = (m + 31) / 32;
   a.uw_words = (n + 3) / 4;
   a.xw_words = (n + 31) / 32;
-  const SlotPlan plan = slot_plan(code, L);
+  const SlotPlan plan = slot_plan(code, L, sh.wpf);
   a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
-  a.event_cap = event_cap(code);
+  a.event_cap = event_cap(code, sh.wpf);
   a.slot_words = plan.slot_words;
   a.slots_off = slots_offset(code, L, sh);
   a.qtab_off = qtab_offset(code, L, sh);

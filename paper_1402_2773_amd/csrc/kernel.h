@@ -41,9 +41,13 @@ constexpr int kListCap = 256;
 // a list entry: the pair's two Philox words, a_k and theta_k of both bits
 constexpr int kEntryWords = 6;
 // the base decoder's list: the pair's two Philox words, a_k of both bits and
-// the pair's index (its thresholds are looked up when the list is finished)
+// a tag (the pair's first bit k0 in bits 0-15, its owner lane in bits 16-21,
+// the pair's slot 2r + p in that lane in bits 22-24; its thresholds are looked
+// up when the list is finished); after the entries, one decision word per
+// lane of the wave, into which the list's decisions are or-ed
 constexpr int kListCapLazy = 192;
 constexpr int kEntryWordsLazy = 5;
+constexpr int kDecisionWords = 64;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 // s_setprio levels of the round phases of the base kernel and of the packed
@@ -284,22 +288,26 @@ __device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t to
 
 // The same for the base decoder's list: a bit's threshold is theta lambda^u
 // with u = t - (its flips so far) (Sec. III-D), looked up here for the listed
-// bits only.
-__device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32_t total, float qs,
-                                                uint32_t pend, uint64_t posb, uint32_t &flip,
-                                                const float *thtab, const uint32_t *fcw, int t,
-                                                float theta, bool adapt, bool fc_bytes) {
+// bits only.  Each entry's two decision bits are or-ed into its owner lane's
+// decision word at the pair's slot (bits 2q2, 2q2 + 1: the owner's flip bits
+// of the pair), which the owner reads once all of the round's entries are
+// finished.
+__device__ __forceinline__ void flush_list_lazy(uint32_t *list, uint32_t *dec, int lane,
+                                                uint32_t total, float qs, const float *thtab,
+                                                const uint32_t *fcw, int t, float theta, bool adapt,
+                                                bool fc_bytes) {
   wave_sync();
   for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
-    uint32_t *ent = list + kEntryWordsLazy * e;
+    const uint32_t *ent = list + kEntryWordsLazy * e;
     float z0, z1;
     bm_pair(ent[0], ent[1], z0, z1);
     const float E0 = __builtin_fmaf(qs, z0, __uint_as_float(ent[2]));
     const float E1 = __builtin_fmaf(qs, z1, __uint_as_float(ent[3]));
+    const uint32_t tag = ent[4];
     float th0 = theta, th1 = theta;
     if (adapt) {
       // the pair's flip counts (bits k0, k0 + 1; k0 even)
-      const uint32_t k0 = ent[4];
+      const uint32_t k0 = tag & 0xFFFFu;
       int f0, f1;
       if (fc_bytes) {
         const uint32_t fc = fcw[k0 >> 2] >> (8 * (k0 & 3u));
@@ -313,17 +321,10 @@ __device__ __forceinline__ void flush_list_lazy(uint32_t *list, int lane, uint32
       th0 = thtab[t - f0];
       th1 = thtab[t - f1];
     }
-    ent[0] = (E0 < th0 ? 1u : 0u) | (E1 < th1 ? 2u : 0u);
+    const uint32_t bits = (E0 < th0 ? 1u : 0u) | (E1 < th1 ? 2u : 0u);
+    if (bits) atomicOr(&dec[(tag >> 16) & 63u], bits << (2 * (tag >> 22)));
   }
-  wave_sync();
-  while (pend) {
-    const int q2 = __builtin_ctz(pend);
-    pend &= pend - 1;
-    const uint32_t ps = (uint32_t)(posb >> (8 * q2)) & 255u;
-    const uint32_t bits = list[kEntryWordsLazy * ps];
-    flip = (flip & ~(3u << (2 * q2))) | (bits << (2 * q2));
-  }
-  wave_sync();
+  wave_sync();  // the decisions have landed; the list is refilled next
 }
 
 // Single-bit rule by bounds: the listed pairs are those with a bit whose E_k
@@ -474,13 +475,18 @@ decode_kernel(DecodeArgs a) {
   uint32_t *fw = xw + a.xw_words;          // [xw_words] flip bits (trace)
   uint32_t *cnt = fw + (TRACE ? a.xw_words : 0);  // unsatisfied checks
   uint32_t *evn = cnt + 1;                 // [2] events listed (rounds alternate)
-  uint32_t *tw = evn + 2;                  // [sw_words] checks toggled this round
+  uint32_t *dl = evn + 2;                  // LZ: [2] change of the unsatisfied count (rounds alternate)
+  uint32_t *tw = dl + 2;                   // [sw_words] checks toggled this round
   uint32_t *evl = tw + a.sw_words;         // [event_cap] toggle events
   uint32_t *fcw = slot + a.fc_off;         // LZ: flip counts, four or two bits per word
   // EXT: [0] argmin key, [1] objective sum; the noise stream
   uint64_t *red = (uint64_t *)(slot + a.red_off);
   float *stream = (float *)(slot + a.stream_off);
   uint32_t *list = lds + a.slots_off + a.frames_per_block * a.slot_words + wave * a.list_words;
+  // LZ: the wave's decision words follow its list entries; zero until a list
+  // entry's decision lands, cleared again by the owner that reads it
+  uint32_t *dec = list + kEntryWordsLazy * kListCapLazy;
+  const uint32_t lane_tag = (uint32_t)lane << 16;
   const bool quant =
       (EXT == kExtMulti || EXT == kExtSingle || EXT == kExtQuantReuse) && a.quant_bits > 0;
   constexpr bool QR = EXT == kExtQuantReuse;
@@ -525,6 +531,7 @@ decode_kernel(DecodeArgs a) {
   // (int16), zero from i = L to the row's end; a lane reads its quad's four
   // samples from two aligned 8-byte words, shifted by the round's phase
   int16_t *qstream = (int16_t *)(slot + a.stream_off);
+  if (LZ) dec[lane] = 0u;
   __syncthreads();
 
   // Frames are handed out from the launch's queue as they are needed, so that
@@ -759,6 +766,13 @@ decode_kernel(DecodeArgs a) {
 
     int t = 0;
     int converged = 0;
+    // LZ: every wave of the frame keeps the unsatisfied count itself, adding
+    // each round's change once the round has ended (so no wave's update can
+    // meet another wave's read of the same round, and the round needs no
+    // barrier between its dense phase and its toggles)
+    uint32_t unsat_reg =
+        LZ ? __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+           : 0u;
     bool mu = true;        // mode switching: multi-bit rounds until f drops
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
@@ -766,7 +780,8 @@ decode_kernel(DecodeArgs a) {
       if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioHead);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedHead);
       const uint32_t unsat =
-          __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+          LZ ? unsat_reg
+             : __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
       // smoothing window t = T-W .. T (Sec. III-E)
       if (W > 0 && t >= T - W) {
 #pragma unroll
@@ -1016,8 +1031,8 @@ decode_kernel(DecodeArgs a) {
         auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
           if (LZ && a.stats && lane == 0) atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)n_listed);
           if (LZ)
-            flush_list_lazy(list, lane, n_listed, qs, pend_, posb_, flip, thtab, fcw, t, a.theta,
-                            adapt, a.fc_bytes != 0);
+            flush_list_lazy(list, dec, lane, n_listed, qs, thtab, fcw, t, a.theta, adapt,
+                            a.fc_bytes != 0);
           else
             flush_list(list, lane, n_listed, qs, pend_, posb_, flip, quant, a.qc, a.qtop);
         };
@@ -1091,10 +1106,13 @@ decode_kernel(DecodeArgs a) {
             if (LZ) settled = fminf(avh[0], avh[1]) >= tc;
             const uint64_t bal = __ballot(!settled);
             if (!settled) {
-              const uint32_t ps = (total + mask_rank(bal)) & 255u;  // < kCap <= 256
+              // total <= kCap - 2 * 64 before a quad, so ps < kCap
+              const uint32_t ps = total + mask_rank(bal);
               const int q2 = 2 * r + p;
-              pend |= 1u << q2;
-              posb |= (uint64_t)ps << (8 * q2);
+              if (!LZ) {
+                pend |= 1u << q2;
+                posb |= (uint64_t)(ps & 255u) << (8 * q2);
+              }
               uint32_t *ent = list + kEW * ps;
               ent[0] = wa;
               ent[1] = wb;
@@ -1102,8 +1120,9 @@ decode_kernel(DecodeArgs a) {
               ent[3] = __float_as_uint(avh[1]);
               if (LZ) {
                 // the pair's first bit, for its flip counts (a lane past the
-                // last quad lists only under a NaN sigma; its bits never flip)
-                ent[4] = (uint32_t)(4 * jc + 2 * p);
+                // last quad lists only under a NaN sigma; its bits never
+                // flip), the owner lane and the pair's slot
+                ent[4] = (uint32_t)(4 * jc + 2 * p) | lane_tag | ((uint32_t)q2 << 22);
               } else {
                 ent[4] = __float_as_uint(thh[0]);
                 ent[5] = __float_as_uint(thh[1]);
@@ -1114,6 +1133,11 @@ decode_kernel(DecodeArgs a) {
         }
         if (LZ) __builtin_amdgcn_s_setprio(kPrioList);
         if (total) drain(total, pend, posb);
+        if (LZ) {
+          // the round's decisions of this lane's listed pairs (0 elsewhere)
+          flip = dec[lane];
+          dec[lane] = 0u;
+        }
       }
 
       // ---- apply: thresholds (Sec. III-D), decisions, syndrome maintenance
@@ -1134,7 +1158,9 @@ decode_kernel(DecodeArgs a) {
           if (j < nq && nib) atomicOr(&fw[j >> 3], nib << (4 * (j & 7)));
         }
       }
-      frame_sync<WPF>();  // every wave has read u before any toggle lands
+      // every wave has read the count before an owner updates it (LZ keeps
+      // its count per wave and needs no barrier here)
+      if (!LZ) frame_sync<WPF>();
       // 1. each flip toggles s_i of its checks: collect the round's toggles in
       //    a bit row (no atomic result is waited for)
       uint32_t *evc = evn + (t & 1);
@@ -1158,6 +1184,9 @@ decode_kernel(DecodeArgs a) {
         }
       }
       frame_sync<WPF>();
+      // LZ: the next round's count-change word (last read at this round's
+      // start, before every wave reached the barrier above)
+      if (LZ && ft == 0) dl[(t + 1) & 1] = 0u;
       // 2. the owner lane of each syndrome word applies its toggles and lists
       //    one event (i, +-1) per toggled check, its slots taken with a single
       //    counter update (owner lanes update the counter at the same time)
@@ -1191,7 +1220,7 @@ decode_kernel(DecodeArgs a) {
           ++slotn;
         }
       }
-      if (dcnt) atomicAdd(cnt, (uint32_t)dcnt);
+      if (dcnt) atomicAdd(LZ ? &dl[t & 1] : cnt, (uint32_t)dcnt);
       if (REG) {
         // 3. every listed event moves u of its check's d_c bits, spread over
         //    all lanes of the frame
@@ -1212,6 +1241,10 @@ decode_kernel(DecodeArgs a) {
         }
       }
       frame_sync<WPF>();
+      // LZ: this round's change of the count (its word was cleared in the
+      // previous round, after every wave had read it), then the other word
+      // is cleared for the next round
+      if (LZ) unsat_reg += __builtin_amdgcn_readfirstlane(__hip_atomic_load(&dl[t & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
       if (TRACE) {
         uint8_t *row = a.trace + ((size_t)f * (size_t)T + (size_t)t) * (size_t)nbytes;
         const uint8_t *fb = (const uint8_t *)fw;
