@@ -339,6 +339,7 @@ struct Layout {
   bool packed = false;  // quantized multi-bit decoder with noise reuse in 16-bit lanes
   bool lazy = true;     // the base decoder: thresholds from a table and flip counts
   bool bounded = false; // single-bit flips with per-bit draws (argmin by bounds)
+  bool one_flip = false; // single-bit rule: one flip, at most a column degree of toggles, per round
   int thr_words = 0;    // the base decoder's table theta lambda^u, u = 0..T (float)
   int t_max = 0;
 };
@@ -368,14 +369,15 @@ struct SlotPlan {
 // the frame (events past the cap are applied by their owners, slower but
 // alike), within the exact range of the kernel's division by d_c; irregular
 // codes apply their toggles directly and list none.
-int event_cap(const ngdbf_code *c, int wpf) {
+int event_cap(const ngdbf_code *c, int wpf, bool one_flip) {
   if (!c->dc) return 0;
-  return std::min(std::min(c->m, 256 * wpf), std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
+  const int cap = std::min(std::min(c->m, 256 * wpf), std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
+  return one_flip ? std::min(cap, 16) : cap;  // one flip toggles at most d_v <= 15 checks
 }
 
 SlotPlan slot_plan(const ngdbf_code *c, const Layout &L, int wpf) {
   int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 5 +
-          (c->m + 31) / 32 + event_cap(c, wpf);
+          (c->m + 31) / 32 + event_cap(c, wpf, L.one_flip);
   SlotPlan p;
   if (L.ext) {
     w = (w + 1) & ~1;
@@ -445,6 +447,7 @@ Layout layout_of(const ngdbf_code *c, const ngdbf_params *p, bool trace) {
   L.packed = packed_decoder(p);
   L.lazy = !L.ext;
   L.bounded = p->variant == NGDBF_SINGLE && !p->noise_reuse;
+  L.one_flip = p->variant == NGDBF_SINGLE;
   L.thr_words = (L.lazy && p->lambda != 1.0f) ? p->t_max + 1 : 0;
   L.t_max = p->t_max;
   return L;
@@ -492,8 +495,10 @@ int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
     if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
     if (wide && sh[0] < 4) continue;
     if (nq <= 64 * sh[0] * sh[1]) {
+      // frames per workgroup: 16, 12, 8, 4, 2, 1 (one if a frame takes several waves)
       Shape cand{sh[0], sh[1], sh[0] == 1 ? 16 : 1};
-      while (check_shape(c, cand, L) != NGDBF_OK && cand.fpb > 1) cand.fpb /= 2;
+      while (check_shape(c, cand, L) != NGDBF_OK && cand.fpb > 1)
+        cand.fpb = cand.fpb == 16 ? 12 : (cand.fpb == 12 ? 8 : cand.fpb / 2);
       if (check_shape(c, cand, L) == NGDBF_OK) {
         *out = cand;
         return ok();
@@ -618,7 +623,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   a.xw_words = (n + 31) / 32;
   const SlotPlan plan = slot_plan(code, L, sh.wpf);
   a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
-  a.event_cap = event_cap(code, sh.wpf);
+  a.event_cap = event_cap(code, sh.wpf, L.one_flip);
   a.slot_words = plan.slot_words;
   a.slots_off = slots_offset(code, L, sh);
   a.qtab_off = qtab_offset(code, L, sh);
@@ -1015,7 +1020,7 @@ ngdbf_status ngdbf_autotune(ngdbf_code *code, const void *y, int64_t n_frames, c
     // more quads per lane or waves per frame than the code needs only idle lanes
     if (ks[1] > 1 && nq <= 64 * ks[0] * (ks[1] / 2)) continue;
     if (ks[0] > 1 && nq <= 64 * (ks[0] / 2) * ks[1]) continue;
-    for (int fpb : {1, 2, 4, 8, 16}) {
+    for (int fpb : {1, 2, 4, 8, 12, 16}) {
       const Shape cand{ks[0], ks[1], fpb};
       if (check_shape(code, cand, layout_of(code, params, false)) != NGDBF_OK) continue;
       Prepared pr;

@@ -119,7 +119,7 @@ def test_variant_parity_c1008_per_frame_sigma(torch_dev, name):
 
 # (waves per frame, quads per lane, frames per block) covering single- and
 # multi-wave frames for C1008 (252 quads)
-SHAPES_1008 = [(1, 4, 2), (1, 4, 8), (2, 2, 1), (4, 1, 1), (8, 1, 1), (16, 1, 1)]
+SHAPES_1008 = [(1, 4, 2), (1, 4, 8), (1, 4, 12), (2, 2, 1), (4, 1, 1), (8, 1, 1), (16, 1, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES_1008, ids=lambda s: "x".join(map(str, s)))
