@@ -652,6 +652,67 @@ def run_single_point(args, workload: str, quiet: bool = False) -> dict:
     return result
 
 
+def run_phases(args) -> int:
+    """Per-round execution counts of the base kernel's data-dependent loops on
+    the headline point (C1008 SM-NGDBF, 3.5 dB; one wavefront per frame, lane
+    l owning bit quads l, l + 64, l + 128, l + 192), from the decoder's own
+    flip traces (ngdbf_decode_trace) and settle-test counters: flips, toggled
+    checks, toggle-loop iterations (most flips of one lane), owner-loop
+    iterations (most toggles in one 32-check word), u-update iterations
+    (events x d_c / 64) and Box-Muller list entries."""
+    import numpy as np
+    import torch
+
+    import paper_1402_2773_amd as ng
+    from paper_1402_2773_amd import sweep
+    from synth import channel, codes
+
+    code_name, ebn0, params, _, _, _ = WORKLOADS[HEADLINE]
+    if args.ebn0 is not None:
+        ebn0, params = args.ebn0, _heur(args.ebn0)
+    seed = 2000 + int(round(ebn0 * 10))
+    c = codes.named_code(code_name)
+    F = args.frames or 1024
+    sigma = float(np.float32(channel.sigma_from_ebn0(ebn0, c.rate)))
+    y = ng.channel(c.n, F, sigma, seed=sweep.channel_seed(seed))
+    dc = ng.Code.from_ldpc(c)
+    counters = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ng.ngdbf_code_set_stats(dc.handle, counters)
+    out = ng.decode(dc, y, sigma, ng.Params(**params), seed, trace=True)
+    torch.cuda.synchronize()
+    ng.ngdbf_code_set_stats(dc.handle, None)
+    Ht = c.dense().astype(np.float32).T
+    tr = np.unpackbits(out.trace.cpu().numpy(), axis=-1, bitorder="little")[..., :c.n]
+    iters = out.iters.cpu().numpy()
+    lane = (np.arange(c.n) // 4) % 64
+    words = (c.m + 31) // 32
+    dcheck = c.nnz // c.m
+    acc = {"flips": [], "toggled_checks": [], "toggle_loop_iterations": [], "owner_loop_iterations": [],
+           "u_update_iterations": []}
+    for f in range(F):
+        m = tr[f, : int(iters[f])].astype(np.float32)          # [rounds, n] flips
+        tg = (m @ Ht).astype(np.int64) & 1                     # [rounds, m] toggled checks
+        per_lane = np.stack([m[:, lane == l].sum(1) for l in range(64)], 1)
+        ev = tg.sum(1)
+        acc["flips"].append(m.sum(1))
+        acc["toggled_checks"].append(ev)
+        acc["toggle_loop_iterations"].append(per_lane.max(1))
+        acc["owner_loop_iterations"].append(
+            np.pad(tg, ((0, 0), (0, 32 * words - c.m))).reshape(len(tg), words, 32).sum(2).max(1))
+        acc["u_update_iterations"].append(-(-ev * dcheck // 64))
+    acc = {k: np.concatenate(v) for k, v in acc.items()}
+    rounds = int(iters.sum())
+    res = {"workload": "phases", "code": code_name, "ebn0_db": ebn0, "frames": F, "rounds": rounds,
+           "avg_iterations": rounds / F,
+           "per_round": {k: float(np.mean(v)) for k, v in acc.items()},
+           "rounds_with_work": float(np.mean(acc["flips"] > 0)),
+           "list_entries_per_round": int(counters[1].item()) / rounds,
+           "pairs_evaluated_per_round": int(counters[0].item()) / rounds}
+    print(json.dumps(res), flush=True)
+    dc.close()
+    return 0
+
+
 def run_issue_rates(args) -> int:
     """Clocks a wave64 vector-ALU instruction of each class holds its SIMD:
     the library's issue probe (long unrolled chains of one class) at eight
@@ -687,8 +748,10 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency", "issue-rates"])
+                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency", "issue-rates", "phases"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
+    ap.add_argument("--ebn0", type=float, default=None,
+                    help="phases: Eb/N0 (dB) of the C1008 SM-NGDBF point (default the headline's)")
     ap.add_argument("--shape", default="", help="fix the launch shape: waves,quads,frames_per_block")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -732,6 +795,8 @@ def main() -> int:
         return run_latency(args)
     if args.workload == "issue-rates":
         return run_issue_rates(args)
+    if args.workload == "phases":
+        return run_phases(args)
     print(json.dumps(run_single_point(args, args.workload)), flush=True)
     return 0
 
