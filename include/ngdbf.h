@@ -47,8 +47,8 @@ typedef enum {
     NGDBF_ENOMEM = -2,       /* device or host allocation failed             */
     NGDBF_EDEVICE = -3,      /* HIP runtime error                             */
     NGDBF_EUNSUPPORTED = -4, /* valid, but outside what the kernels support  */
-    NGDBF_EBUSY = -5         /* every frame queue of the device is held by a
-                                launch still in flight (see ngdbf_decode)     */
+    NGDBF_EBUSY = -5         /* the frame queue a launch would take is still
+                                held by a launch in flight (see ngdbf_decode) */
 } ngdbf_status;
 
 /* Opaque handle: a parity-check matrix H resident on one device. */
@@ -149,14 +149,18 @@ ngdbf_status ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  * counters of frame runs plus a count of finished waves, reset by the launch
  * itself when it ends).  Direct launches take queues from one ring of 1024,
  * launches recorded under stream capture from another ring of 1024, so a
- * graph's launches never share a queue with direct launches.  At most 1024
- * direct launches may be in flight at once; at most 1024 recorded launches
- * may belong to graphs replayed at the same time; a captured graph must not
- * be replayed on two streams at the same time.  With trace rows, the rows
+ * graph's launches never share a queue with direct launches.  An event
+ * recorded after each direct launch marks its queue free again: a direct
+ * launch that would take a queue still held by a launch in flight (1024
+ * launches queued on streams and not yet finished) returns NGDBF_EBUSY and
+ * launches nothing.  At most 1024 recorded launches may belong to graphs
+ * replayed at the same time; a captured graph must not be replayed on two
+ * streams at the same time.  With trace rows, the rows
  * are cleared by a kernel on `stream` before the decode (no memset node
  * under capture).
  * Errors: NGDBF_EINVAL (NULL pointers with n_frames > 0, parameters out of
- * range), NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
+ * range), NGDBF_EBUSY (its queue still held, see above),
+ * NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
  */
 ngdbf_status ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames,
                  const float *sigma, float sigma_scalar,

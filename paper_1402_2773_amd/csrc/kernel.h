@@ -1177,26 +1177,40 @@ decode_kernel(DecodeArgs a) {
             atomicAdd(&fcw[k >> 1], 1u << (16 * (k & 1)));
         }
         const int c0 = REG ? (int)__umul24(k, a.dv) : tab.col_ptr[k];
-        const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
-        for (int e = c0; e < c1; ++e) {
-          const int i = tab.row_idx[e];
-          atomicXor(&tw[i >> 5], 1u << (i & 31));
+        if (REG && a.dv == 3) {
+          // the common column weight, unrolled (a wave-uniform branch)
+          const int i0 = tab.row_idx[c0], i1 = tab.row_idx[c0 + 1], i2 = tab.row_idx[c0 + 2];
+          atomicXor(&tw[i0 >> 5], 1u << (i0 & 31));
+          atomicXor(&tw[i1 >> 5], 1u << (i1 & 31));
+          atomicXor(&tw[i2 >> 5], 1u << (i2 & 31));
+        } else {
+          const int c1 = REG ? c0 + a.dv : tab.col_ptr[k + 1];
+          for (int e = c0; e < c1; ++e) {
+            const int i = tab.row_idx[e];
+            atomicXor(&tw[i >> 5], 1u << (i & 31));
+          }
         }
       }
       frame_sync<WPF>();
       // LZ: the next round's count-change word (last read at this round's
       // start, before every wave reached the barrier above)
       if (LZ && ft == 0) dl[(t + 1) & 1] = 0u;
-      // 2. the owner lane of each syndrome word applies its toggles and lists
-      //    one event (i, +-1) per toggled check, its slots taken with a single
-      //    counter update (owner lanes update the counter at the same time)
+      // 2. the owner lane of each byte of s (eight checks) applies its
+      //    toggles and lists one event (i, +-1) per toggled check, its slots
+      //    taken with a single counter update (owner lanes update the counter
+      //    at the same time).  A word's four owners are adjacent lanes of one
+      //    wave: all four read the word before the first clears it, and each
+      //    writes back only its own byte of s.
       int32_t dcnt = 0;
-      for (int wd = ft; wd < a.sw_words; wd += FT) {
-        const uint32_t tg = tw[wd];
+      for (int bt = ft; bt < 4 * a.sw_words; bt += FT) {
+        const int wd = bt >> 2;
+        const int sh = 8 * (bt & 3);
+        const uint32_t tword = tw[wd];
+        if ((bt & 3) == 0 && tword) tw[wd] = 0u;
+        const uint32_t tg = (tword >> sh) & 255u;
         if (!tg) continue;
-        const uint32_t sn = sw[wd] ^ tg;
-        sw[wd] = sn;
-        tw[wd] = 0u;
+        const uint32_t sn = ((sw[wd] >> sh) & 255u) ^ tg;
+        reinterpret_cast<uint8_t *>(sw)[bt] = (uint8_t)sn;
         dcnt += 2 * __builtin_popcount(sn & tg) - __builtin_popcount(tg);
         const uint32_t ecap = (uint32_t)a.event_cap;
         uint32_t slotn = REG ? atomicAdd(evc, (uint32_t)__builtin_popcount(tg)) : ecap;
@@ -1204,7 +1218,7 @@ decode_kernel(DecodeArgs a) {
         while (bits) {
           const int bb = __builtin_ctz(bits);
           bits &= bits - 1;
-          const int i = 32 * wd + bb;
+          const int i = 8 * bt + bb;
           const bool unsat_now = ((sn >> bb) & 1u) != 0u;
           if (slotn < ecap) {
             evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
