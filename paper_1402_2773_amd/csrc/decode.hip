@@ -375,6 +375,18 @@ int event_cap(const ngdbf_code *c, int wpf, bool one_flip) {
   return one_flip ? std::min(cap, 16) : cap;  // one flip toggles at most d_v <= 15 checks
 }
 
+// Rounds that start with more unsatisfied checks than this list no events:
+// the owner of each byte of s applies its toggled checks' d_c updates of u
+// itself.  That pays where the checks give every other lane of the frame a
+// byte to own and rows are light (d_c <= 8) and the round is busy; light
+// rounds and heavy rows list their events and spread the updates over all
+// lanes.
+constexpr uint32_t kListUnsatMax = 64;
+uint32_t list_unsat_max(const ngdbf_code *c, int wpf) {
+  if (c->dc && c->dc <= 8 && (c->m + 7) / 8 >= 32 * wpf) return kListUnsatMax;
+  return 0xFFFFFFFFu;
+}
+
 SlotPlan slot_plan(const ngdbf_code *c, const Layout &L, int wpf) {
   int w = (c->m + 31) / 32 + (c->n + 3) / 4 + ((c->n + 31) / 32) * (L.trace ? 2 : 1) + 5 +
           (c->m + 31) / 32 + event_cap(c, wpf, L.one_flip);
@@ -624,6 +636,7 @@ int prepare(const ngdbf_code *code, const void *y, int64_t n_frames, const float
   const SlotPlan plan = slot_plan(code, L, sh.wpf);
   a.dc_recip = code->dc ? (uint32_t)(((1u << 20) + code->dc - 1) / code->dc) : 0u;
   a.event_cap = event_cap(code, sh.wpf, L.one_flip);
+  a.list_unsat_max = list_unsat_max(code, sh.wpf);
   a.slot_words = plan.slot_words;
   a.slots_off = slots_offset(code, L, sh);
   a.qtab_off = qtab_offset(code, L, sh);

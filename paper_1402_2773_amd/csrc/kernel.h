@@ -51,8 +51,13 @@ constexpr int kDecisionWords = 64;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 // s_setprio levels of the round phases of the base kernel and of the packed
-// quantized decoder (which has no list)
+// quantized decoder (which has no list).  With one wave per frame the dense
+// phase runs highest and the list lowest (other frames' waves fill the SIMD
+// while a wave finishes its list).  A frame of several waves meets at
+// workgroup barriers, so there the later a phase is in the round the higher
+// it runs: waves that lag behind their frame catch up first.
 constexpr int kPrioHead = 1, kPrioDense = 3, kPrioList = 0, kPrioSyndrome = 2;
+constexpr int kPrioHeadMulti = 0, kPrioDenseMulti = 1, kPrioListMulti = 2, kPrioSyndromeMulti = 3;
 constexpr int kPrioPackedHead = 1, kPrioPackedDense = 2, kPrioPackedSyndrome = 3;
 
 // decode_kernel's EXT argument: which decoder family the instance holds
@@ -104,6 +109,8 @@ struct DecodeArgs {
   int32_t sw_words, uw_words, xw_words;   // per-slot LDS arrays
   uint32_t dc_recip;                      // ceil(2^20 / d_c) for regular codes
   int32_t event_cap;                      // check-toggle events per frame and round held
+  uint32_t list_unsat_max;                // rounds starting with more unsatisfied checks
+                                          // apply events without listing them
                                           // for the parallel u update (0: irregular code)
   int32_t slot_words;                     // LDS words per frame slot (even)
   int32_t slots_off;                      // LDS word offset of the frame slots (even)
@@ -777,7 +784,7 @@ decode_kernel(DecodeArgs a) {
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
     for (;; ++t) {
-      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioHead);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioHead : kPrioHeadMulti);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedHead);
       const uint32_t unsat =
           LZ ? unsat_reg
@@ -927,7 +934,7 @@ decode_kernel(DecodeArgs a) {
         // through the transform.
         auto bound_single = [&](auto quant_c) -> uint64_t {
           constexpr bool kQuant = decltype(quant_c)::value;
-          __builtin_amdgcn_s_setprio(kPrioDense);
+          __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioDense : kPrioDenseMulti);
           Words4 wq[QPL];
           float avq[QPL * 4];
           float ub = INFINITY;
@@ -996,7 +1003,7 @@ decode_kernel(DecodeArgs a) {
               total += (uint32_t)__popcll(bal);
             }
           }
-          __builtin_amdgcn_s_setprio(kPrioList);
+          __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioList : kPrioListMulti);
           if (total) flush_single(list, lane, total, qs, kQuant, a.qc, a.qtop, n, bl);
           return bl;
         };
@@ -1040,7 +1047,7 @@ decode_kernel(DecodeArgs a) {
         // first word has c leading zeros, the float above theta_max + B_c,
         // with theta_max the largest threshold a bit can hold in round t:
         // theta_t for theta <= 0, theta itself for theta > 0
-        if (LZ) __builtin_amdgcn_s_setprio(kPrioDense);
+        if (LZ) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioDense : kPrioDenseMulti);
         const float tl = LZ ? next_up((a.theta > 0.0f ? a.theta : tht) + bcl) : 0.0f;
         const PhiloxRound pr = philox_round((uint32_t)t, fr_lo, key0, key1);
         uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
@@ -1131,7 +1138,7 @@ decode_kernel(DecodeArgs a) {
             total += (uint32_t)__popcll(bal);
           }
         }
-        if (LZ) __builtin_amdgcn_s_setprio(kPrioList);
+        if (LZ) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioList : kPrioListMulti);
         if (total) drain(total, pend, posb);
         if (LZ) {
           // the round's decisions of this lane's listed pairs (0 elsewhere)
@@ -1148,7 +1155,7 @@ decode_kernel(DecodeArgs a) {
           if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
       }
       xneg ^= flip;
-      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioSyndrome);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioSyndrome : kPrioSyndromeMulti);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedSyndrome);
       if (TRACE) {
 #pragma unroll
@@ -1201,6 +1208,12 @@ decode_kernel(DecodeArgs a) {
       //    at the same time).  A word's four owners are adjacent lanes of one
       //    wave: all four read the word before the first clears it, and each
       //    writes back only its own byte of s.
+      //    Rounds that start with many unsatisfied checks (many flips) list
+      //    nothing: each owner applies its events' d_c updates of u itself,
+      //    which then costs less than listing and spreading them (the
+      //    choice is uniform over the frame: every wave holds the same count).
+      const uint32_t ecap = (uint32_t)a.event_cap;
+      const bool listing = REG && ecap && unsat <= a.list_unsat_max;
       int32_t dcnt = 0;
       for (int bt = ft; bt < 4 * a.sw_words; bt += FT) {
         const int wd = bt >> 2;
@@ -1212,30 +1225,56 @@ decode_kernel(DecodeArgs a) {
         const uint32_t sn = ((sw[wd] >> sh) & 255u) ^ tg;
         reinterpret_cast<uint8_t *>(sw)[bt] = (uint8_t)sn;
         dcnt += 2 * __builtin_popcount(sn & tg) - __builtin_popcount(tg);
-        const uint32_t ecap = (uint32_t)a.event_cap;
-        uint32_t slotn = REG ? atomicAdd(evc, (uint32_t)__builtin_popcount(tg)) : ecap;
-        uint32_t bits = tg;
-        while (bits) {
-          const int bb = __builtin_ctz(bits);
-          bits &= bits - 1;
-          const int i = 8 * bt + bb;
-          const bool unsat_now = ((sn >> bb) & 1u) != 0u;
-          if (slotn < ecap) {
-            evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
+        // event (check i, +-1) applied here: d_c updates of u
+        auto apply = [&](int i, bool unsat_now, bool unrolled) {
+          const uint32_t d = unsat_now ? 1u : 0xFFFFFFFFu;
+          const int r0 = tab.row_begin(i);
+          if (unrolled) {
+            int k2[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) k2[j] = tab.col_idx[r0 + j];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) atomicAdd(&uw[k2[j] >> 2], d << (8 * (k2[j] & 3)));
           } else {
-            // list full (or an irregular code): apply the event here
-            const uint32_t d = unsat_now ? 1u : 0xFFFFFFFFu;
-            const int r0 = tab.row_begin(i), r1 = tab.row_end(i);
+            const int r1 = tab.row_end(i);
             for (int e2 = r0; e2 < r1; ++e2) {
               const int k2 = tab.col_idx[e2];
               atomicAdd(&uw[k2 >> 2], d << (8 * (k2 & 3)));
             }
           }
-          ++slotn;
+        };
+        uint32_t bits = tg;
+        if (listing) {
+          uint32_t slotn = atomicAdd(evc, (uint32_t)__builtin_popcount(tg));
+          while (bits) {
+            const int bb = __builtin_ctz(bits);
+            bits &= bits - 1;
+            const int i = 8 * bt + bb;
+            const bool unsat_now = ((sn >> bb) & 1u) != 0u;
+            if (slotn < ecap)
+              evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
+            else
+              apply(i, unsat_now, false);  // list full: apply the event here
+            ++slotn;
+          }
+        } else if (REG && a.dc == 6) {
+          // no list, the common row weight: unrolled (a wave-uniform branch)
+          while (bits) {
+            const int bb = __builtin_ctz(bits);
+            bits &= bits - 1;
+            apply(8 * bt + bb, ((sn >> bb) & 1u) != 0u, true);
+          }
+        } else {
+          // no list, or an irregular code
+          while (bits) {
+            const int bb = __builtin_ctz(bits);
+            bits &= bits - 1;
+            apply(8 * bt + bb, ((sn >> bb) & 1u) != 0u, false);
+          }
         }
       }
       if (dcnt) atomicAdd(LZ ? &dl[t & 1] : cnt, (uint32_t)dcnt);
-      if (REG) {
+      if (listing) {
         // 3. every listed event moves u of its check's d_c bits, spread over
         //    all lanes of the frame
         frame_sync<WPF>();
