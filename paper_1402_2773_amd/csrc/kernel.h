@@ -1202,6 +1202,11 @@ decode_kernel(DecodeArgs a) {
       // LZ: the next round's count-change word (last read at this round's
       // start, before every wave reached the barrier above)
       if (LZ && ft == 0) dl[(t + 1) & 1] = 0u;
+      // LZ, one wave per frame: a round without flips has no syndrome update
+      // (frames of several waves would need one more exchange to agree on
+      // that, which costs more than the update it saves)
+      const bool any_flip = !(LZ && WPF == 1) || __builtin_amdgcn_ballot_w64(flip != 0u) != 0ull;
+      if (any_flip) {
       // 2. the owner lane of each byte of s (eight checks) applies its
       //    toggles and lists one event (i, +-1) per toggled check, its slots
       //    taken with a single counter update (owner lanes update the counter
@@ -1298,6 +1303,7 @@ decode_kernel(DecodeArgs a) {
       // previous round, after every wave had read it), then the other word
       // is cleared for the next round
       if (LZ) unsat_reg += __builtin_amdgcn_readfirstlane(__hip_atomic_load(&dl[t & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+      }  // any_flip
       if (TRACE) {
         uint8_t *row = a.trace + ((size_t)f * (size_t)T + (size_t)t) * (size_t)nbytes;
         const uint8_t *fb = (const uint8_t *)fw;
