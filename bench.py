@@ -658,7 +658,9 @@ def run_phases(args) -> int:
     l owning bit quads l, l + 64, l + 128, l + 192), from the decoder's own
     flip traces (ngdbf_decode_trace) and settle-test counters: flips, toggled
     checks, toggle-loop iterations (most flips of one lane), owner-loop
-    iterations (most toggles in one 32-check word), u-update iterations
+    iterations (most toggles in one 8-check byte of s), the share of rounds
+    whose owners apply their events unlisted (more than 64 unsatisfied
+    checks at the round's start), u-update passes of the listing rounds
     (events x d_c / 64) and Box-Muller list entries."""
     import numpy as np
     import torch
@@ -684,28 +686,40 @@ def run_phases(args) -> int:
     Ht = c.dense().astype(np.float32).T
     tr = np.unpackbits(out.trace.cpu().numpy(), axis=-1, bitorder="little")[..., :c.n]
     iters = out.iters.cpu().numpy()
+    x0 = (y.cpu().numpy() < 0).astype(np.float32)            # hard-decision errors (all-zero word)
     lane = (np.arange(c.n) // 4) % 64
-    words = (c.m + 31) // 32
+    sbytes = (c.m + 7) // 8
     dcheck = c.nnz // c.m
-    acc = {"flips": [], "toggled_checks": [], "toggle_loop_iterations": [], "owner_loop_iterations": [],
-           "u_update_iterations": []}
+    acc = {"flips": [], "toggled_checks": [], "unsatisfied_at_start": [], "toggle_loop_iterations": [],
+           "owner_loop_iterations": [], "u_update_iterations": [], "direct": []}
     for f in range(F):
         m = tr[f, : int(iters[f])].astype(np.float32)          # [rounds, n] flips
+        if not len(m):
+            continue
         tg = (m @ Ht).astype(np.int64) & 1                     # [rounds, m] toggled checks
+        xe = (x0[f] + np.vstack([np.zeros((1, c.n), np.float32), np.cumsum(m, 0)[:-1]])) % 2
+        unsat = ((xe @ Ht).astype(np.int64) & 1).sum(1)        # unsatisfied checks at each round's start
         per_lane = np.stack([m[:, lane == l].sum(1) for l in range(64)], 1)
         ev = tg.sum(1)
+        direct = unsat > 64                                   # rounds whose owners apply events unlisted
         acc["flips"].append(m.sum(1))
         acc["toggled_checks"].append(ev)
+        acc["unsatisfied_at_start"].append(unsat)
         acc["toggle_loop_iterations"].append(per_lane.max(1))
         acc["owner_loop_iterations"].append(
-            np.pad(tg, ((0, 0), (0, 32 * words - c.m))).reshape(len(tg), words, 32).sum(2).max(1))
-        acc["u_update_iterations"].append(-(-ev * dcheck // 64))
+            np.pad(tg, ((0, 0), (0, 8 * sbytes - c.m))).reshape(len(tg), sbytes, 8).sum(2).max(1))
+        acc["u_update_iterations"].append(np.where(direct, 0, -(-ev * dcheck // 64)))
+        acc["direct"].append(direct.astype(np.float64))
     acc = {k: np.concatenate(v) for k, v in acc.items()}
     rounds = int(iters.sum())
     res = {"workload": "phases", "code": code_name, "ebn0_db": ebn0, "frames": F, "rounds": rounds,
            "avg_iterations": rounds / F,
            "per_round": {k: float(np.mean(v)) for k, v in acc.items()},
            "rounds_with_work": float(np.mean(acc["flips"] > 0)),
+           "direct_rounds": float(np.mean(acc["direct"])),
+           "owner_loop_iterations_per_round_by_kind": {
+               "listing": float(np.sum(acc["owner_loop_iterations"] * (1 - acc["direct"])) / len(acc["direct"])),
+               "direct": float(np.sum(acc["owner_loop_iterations"] * acc["direct"]) / len(acc["direct"]))},
            "list_entries_per_round": int(counters[1].item()) / rounds,
            "pairs_evaluated_per_round": int(counters[0].item()) / rounds}
     print(json.dumps(res), flush=True)
