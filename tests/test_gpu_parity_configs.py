@@ -241,3 +241,40 @@ def test_binary32_against_binary64_headline(torch_dev):
     assert same > 0.99
     del y, out
     torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------- busy rounds
+
+def _round_stats(c, y, trace, iters):
+    """Per round: unsatisfied checks at its start and checks it toggles."""
+    ht = c.dense().astype(np.float32).T
+    x0 = (y < 0).astype(np.float32)
+    fl = oracle.unpack_bits(trace, c.n).astype(np.float32)
+    unsat, events = [], []
+    for f in range(len(y)):
+        m = fl[f, : int(iters[f])]
+        if not len(m):
+            continue
+        xe = (x0[f] + np.vstack([np.zeros((1, c.n), np.float32), np.cumsum(m, 0)[:-1]])) % 2
+        unsat.append(((xe @ ht).astype(np.int64) & 1).sum(1))
+        events.append(((m @ ht).astype(np.int64) & 1).sum(1))
+    return np.concatenate(unsat), np.concatenate(events)
+
+
+@pytest.mark.parametrize("name,frames,event_list", [("C1008", 200, 256), ("C4000", 40, 1024)])
+def test_busy_rounds_unlisted_and_full_event_list(torch_dev, name, frames, event_list):
+    """A threshold above most a_k with strong perturbation flips about half
+    the bits of a round (Sec. III-B Step 3b), so about half the checks
+    toggle: rounds that start with more than 64 unsatisfied checks have their
+    events applied by the owners of s without a list, and rounds that start
+    with fewer can toggle more checks than the frame's event list holds (256
+    per wave), so the owners apply the excess themselves.  Whole flip traces
+    must still match the oracle's."""
+    c, _ = dev_code(name)
+    y = channel.bpsk_awgn(frames, c.n, 0.3, seed=41)
+    p = oracle.Params(w=0.75, theta=3.0, lam=1.0, eta=1.0, ymax=2.5, t_max=12, smooth_window=0)
+    say(f"busy rounds {name} frames={frames}")
+    r = run_both(torch_dev, name, y, 1.0, p, seed=43, trace=True)
+    unsat, events = _round_stats(c, y, r.trace, r.iters)
+    assert (unsat > 64).sum() > 50, "the case must hold rounds applied without a list"
+    assert ((unsat <= 64) & (events > event_list)).sum() >= 1, "the case must overflow the event list"
