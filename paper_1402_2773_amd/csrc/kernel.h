@@ -300,11 +300,12 @@ __device__ __forceinline__ void flush_list(uint32_t *list, int lane, uint32_t to
 // of the pair), which the owner reads once all of the round's entries are
 // finished.
 __device__ __forceinline__ void flush_list_lazy(uint32_t *list, uint32_t *dec, int lane,
-                                                uint32_t total, float qs, const float *thtab,
+                                                uint32_t first, uint32_t total, float qs,
+                                                const float *thtab,
                                                 const uint32_t *fcw, int t, float theta, bool adapt,
                                                 bool fc_bytes) {
   wave_sync();
-  for (uint32_t e = (uint32_t)lane; e < total; e += kWave) {
+  for (uint32_t e = first + (uint32_t)lane; e < total; e += kWave) {
     const uint32_t *ent = list + kEntryWordsLazy * e;
     float z0, z1;
     bm_pair(ent[0], ent[1], z0, z1);
@@ -1035,10 +1036,12 @@ decode_kernel(DecodeArgs a) {
         // thresholds looked up; otherwise six words with theta_k in them
         constexpr uint32_t kCap = LZ ? (uint32_t)kListCapLazy : (uint32_t)kListCap;
         constexpr int kEW = LZ ? kEntryWordsLazy : kEntryWords;
-        auto drain = [&](uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
-          if (LZ && a.stats && lane == 0) atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)n_listed);
+        // (LZ: entries [first, n_listed) of the list)
+        auto drain = [&](uint32_t first, uint32_t n_listed, uint32_t pend_, uint64_t posb_) {
+          if (LZ && a.stats && lane == 0)
+            atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)(n_listed - first));
           if (LZ)
-            flush_list_lazy(list, dec, lane, n_listed, qs, thtab, fcw, t, a.theta, adapt,
+            flush_list_lazy(list, dec, lane, first, n_listed, qs, thtab, fcw, t, a.theta, adapt,
                             a.fc_bytes != 0);
           else
             flush_list(list, lane, n_listed, qs, pend_, posb_, flip, quant, a.qc, a.qtop);
@@ -1056,11 +1059,20 @@ decode_kernel(DecodeArgs a) {
   #pragma unroll
         for (int r = 0; r < QPL; ++r) {
           // a quad adds at most 2 * 64 entries: drain the list first if needed
-          if (r > 0 && total > kCap - 2 * kWave) {
-            drain(total, pend, posb);
-            total = 0;
-            pend = 0;
-            posb = 0;
+          // (LZ: whole passes of 64 from the list's end, keeping the first
+          // total mod 64 entries for a later pass, so no pass runs part-empty
+          // before the round's last)
+          if (r > 0 && __builtin_expect(total > kCap - 2 * kWave, 0)) {
+            if (LZ) {
+              const uint32_t keep = total & (uint32_t)(kWave - 1);
+              drain(keep, total, 0u, 0ull);
+              total = keep;
+            } else {
+              drain(0u, total, pend, posb);
+              total = 0;
+              pend = 0;
+              posb = 0;
+            }
           }
           const int j = ft + FT * r;
           // lanes past the last quad run the same code on a clamped index;
@@ -1139,7 +1151,7 @@ decode_kernel(DecodeArgs a) {
           }
         }
         if (LZ) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioList : kPrioListMulti);
-        if (total) drain(total, pend, posb);
+        if (total) drain(0u, total, pend, posb);
         if (LZ) {
           // the round's decisions of this lane's listed pairs (0 elsewhere)
           flip = dec[lane];
