@@ -791,7 +791,7 @@ decode_kernel(DecodeArgs a) {
           LZ ? unsat_reg
              : __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
       // smoothing window t = T-W .. T (Sec. III-E)
-      if (W > 0 && t >= T - W) {
+      if (__builtin_expect(W > 0 && t >= T - W, 0)) {
 #pragma unroll
         for (int q = 0; q < QPL * 4; ++q)
           X2[q >> 1] += (((xneg >> q) & 1u) ? 0xFFFFFFFFu : 1u) << (16 * (q & 1));
@@ -815,7 +815,7 @@ decode_kernel(DecodeArgs a) {
         if (t > 0 && fx < f_prev) mu = false;
         f_prev = fx;
       }
-      if (unsat == 0) {
+      if (__builtin_expect(unsat == 0, 0)) {
         converged = 1;
         break;
       }
@@ -1268,7 +1268,7 @@ decode_kernel(DecodeArgs a) {
             bits &= bits - 1;
             const int i = 8 * bt + bb;
             const bool unsat_now = ((sn >> bb) & 1u) != 0u;
-            if (slotn < ecap)
+            if (__builtin_expect(slotn < ecap, 1))
               evl[slotn] = ((uint32_t)i << 1) | (unsat_now ? 0u : 1u);
             else
               apply(i, unsat_now, false);  // list full: apply the event here
