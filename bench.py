@@ -94,9 +94,12 @@ HEADLINE = "c1008_sm_3.5dB"
 DEFAULT = "mix4"
 
 # launch shapes (waves per frame, quads per lane, frames per workgroup) for
-# workloads whose default shape is slower (none at present: the library's
-# default is the fastest timed shape for every workload here)
-WORKLOAD_SHAPES = {}
+# workloads whose default shape is slower: the (6,32) code's searched
+# parameter set converges in 12-15 rounds, where four waves per frame with
+# two quads per lane beat the default two waves with four quads (84.9 against
+# 89.2 ms, int8 73.5 against 75.4); the default wins on the long frames of
+# the paper's own parameter set (449 against 476 ms) and the mixed batch
+WORKLOAD_SHAPES = {"c2048_tuned_4.5dB_f32": (4, 2, 1), "c2048_tuned_4.5dB_i8": (4, 2, 1)}
 
 # Batched multi-code workload: the four codes in frame proportions 4:2:1:1,
 # per-frame Eb/N0 uniform in [2, 5] dB, per-code parameters as above

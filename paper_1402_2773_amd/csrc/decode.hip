@@ -413,9 +413,9 @@ SlotPlan slot_plan(const ngdbf_code *c, const Layout &L, int wpf) {
   return p;
 }
 
-// The base kernel with four or more waves per frame reads the code tables
+// The base kernel with two or more waves per frame reads the code tables
 // from global memory (the kernel's TG); every other instance stages them.
-bool tables_in_lds(const Layout &L, const Shape &sh) { return !(L.lazy && sh.wpf >= 4); }
+bool tables_in_lds(const Layout &L, const Shape &sh) { return !(L.lazy && sh.wpf >= 2); }
 
 // LDS words: [code tables] | [threshold table] | frame slots | wave lists
 int qtab_offset(const ngdbf_code *c, const Layout &L, const Shape &sh) {
@@ -499,13 +499,12 @@ int pick_shape(const ngdbf_code *c, const Layout &L, Shape *out) {
   // the single-bit decoder by bounds runs faster with one wave per frame,
   // which saves its frame-wide reductions their barriers)
   const bool few_quads = L.ext && !L.packed && !L.bounded;
-  // the base kernel's frames of more than one wave take four or more waves
-  // (code tables outside the LDS, more workgroups per CU: C2048 at (4, 2)
-  // runs twice as fast as at (2, 4))
-  const bool wide = L.lazy && nq > 64 * 4;
+  // the base kernel's frames of more than one wave read the code tables from
+  // global memory (more workgroups per CU); for codes above 1024 bits the
+  // fewest waves that hold the code win (C2048 at (2, 4) in 199 ms against
+  // 216 at (4, 2) on a mixed-SNR batch)
   for (const auto &sh : kShapes) {
     if (few_quads && sh[1] > 2 && nq <= 64 * 16) continue;
-    if (wide && sh[0] < 4) continue;
     if (nq <= 64 * sh[0] * sh[1]) {
       // frames per workgroup: 16, 12, 8, 4, 2, 1 (one if a frame takes several waves)
       Shape cand{sh[0], sh[1], sh[0] == 1 ? 16 : 1};

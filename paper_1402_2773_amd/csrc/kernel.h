@@ -5,7 +5,7 @@
 //   HBM: y frame-major [F][n] (float32 or int8), sigma [F], outputs
 //        out_bits [F][ceil(n/8)], out_iters [F], out_converged [F].
 //   Code tables: uint16 N(i) (CSR) and M(k) (CSC), staged into LDS once per
-//        workgroup (read from global memory by the base kernel with four or
+//        workgroup (read from global memory by the base kernel with two or
 //        more waves per frame).
 //   LDS per frame: syndrome bits s, per-bit counts u_k of unsatisfied checks,
 //        the unsatisfied-check count, an x / flip bit row, a toggle row and a
@@ -438,8 +438,8 @@ struct Tables {
 // drawn once into LDS; bit k reads element n - 1 + t - k in round t).
 
 // Occupancy target: four waves per SIMD; the base kernel with four or more
-// waves per frame (code tables outside the LDS) aims higher when each lane
-// holds fewer quads.
+// waves per frame (code tables outside the LDS, as for two) aims higher when
+// each lane holds fewer quads.
 template <int WPF, int QPL, int EXT>
 constexpr int waves_per_simd() {
   return (EXT == kExtNone && WPF >= 4) ? (QPL == 1 ? 8 : (QPL == 2 ? 6 : 4)) : 4;
@@ -462,10 +462,10 @@ decode_kernel(DecodeArgs a) {
   const int nbytes = (n + 7) >> 3;
   const int T = a.t_max, W = a.smooth_window;
 
-  // stage the code tables once per workgroup; the base kernel with four or
+  // stage the code tables once per workgroup; the base kernel with two or
   // more waves per frame reads them from global memory through the caches
   // instead (a frame is a workgroup there, and the LDS goes to more of them)
-  constexpr bool TG = EXT == kExtNone && WPF >= 4;
+  constexpr bool TG = EXT == kExtNone && WPF >= 2;
   if (!TG)
     for (int i = tid; i < a.table_words; i += blockDim.x) lds[i] = a.tables[i];
   const uint16_t *t16 = TG ? (const uint16_t *)a.tables : (const uint16_t *)lds;

@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # decode-kernel template arguments (waves per frame, quads per lane) -> code
-MIX4_INSTANCES = {(1, 1): "C96", (1, 4): "C1008", (4, 2): "C2048", (4, 4): "C4000"}
+MIX4_INSTANCES = {(1, 1): "C96", (1, 4): "C1008", (2, 4): "C2048", (4, 4): "C4000"}
 
 
 def dispatches(path):
