@@ -228,8 +228,9 @@ ngdbf_status ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
  *   waves_per_frame : wavefronts cooperating on one frame (1, 2, 4, 8, 16);
  *   quads_per_lane  : bit quads each lane owns (1, 2, 4); a frame holds at most
  *                     64 * waves_per_frame * quads_per_lane quads (4 bits each);
- *   frames_per_block: frames per workgroup (1 unless waves_per_frame == 1, then
- *                     2, 4, 8 or 16).
+ *   frames_per_block: frames per workgroup: 1 when waves_per_frame > 1, else
+ *                     1 .. 16 (the default takes the first of 16, 12, 8, 4,
+ *                     2, 1 that the LDS holds).
  * ngdbf_code_set_shape fixes the shape used by later decodes of this code
  * (NGDBF_EINVAL if it does not fit the code, NGDBF_EUNSUPPORTED if it was not
  * built or exceeds the LDS); all-zero arguments restore the default choice.
@@ -239,7 +240,10 @@ ngdbf_status ngdbf_noise_probe(int32_t kind, uint32_t start, uint32_t count,
  * reuse, single-bit with noise reuse, mode switching) take at most two quads
  * per lane (more waves per frame); the base decoder, the packed quantized
  * decoder with noise reuse and the single-bit decoder with per-bit draws take
- * one wave per frame whenever the code fits in 1024 bits.
+ * one wave per frame whenever the code fits in 1024 bits; longer codes take
+ * the fewest waves that hold them (the base decoder: two waves of four quads
+ * up to 2048 bits, then four waves of four quads; its frames of two or more
+ * waves read the code tables from global memory instead of the LDS).
  * Not thread-safe against concurrent decodes of the same code.
  */
 ngdbf_status ngdbf_code_set_shape(ngdbf_code *code, int32_t waves_per_frame,

@@ -111,6 +111,12 @@ def test_shape_validation(torch_dev):
     pl = ng.Params(quant_bits=4, noise_reuse=1, ymax=1.75, t_max=4000).c(ng.NGDBF_Y_F32)
     assert ng.ngdbf_code_get_shape(dc.handle, pl)[:2] == (1, 4)
     dc.close()
+    # longer codes: the fewest waves that hold them (the base decoder's frames
+    # of several waves read their tables from global memory)
+    for name, shape in (("C2048", (2, 4, 1)), ("C4000", (4, 4, 1))):
+        dl = ng.Code.from_ldpc(codes.named_code(name))
+        assert ng.ngdbf_code_get_shape(dl.handle) == shape, name
+        dl.close()
 
 
 def test_autotune_keeps_results(torch_dev):
