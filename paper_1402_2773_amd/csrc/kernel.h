@@ -51,13 +51,11 @@ constexpr int kDecisionWords = 64;
 // smoothing counters are 16-bit halves biased by this value
 constexpr uint32_t kXBias = 32768u;
 // s_setprio levels of the round phases of the base kernel and of the packed
-// quantized decoder (which has no list).  With one wave per frame the dense
-// phase runs highest and the list lowest (other frames' waves fill the SIMD
-// while a wave finishes its list).  A frame of several waves meets at
-// workgroup barriers, so there the later a phase is in the round the higher
-// it runs: waves that lag behind their frame catch up first.
-constexpr int kPrioHead = 1, kPrioDense = 3, kPrioList = 0, kPrioSyndrome = 2;
-constexpr int kPrioHeadMulti = 0, kPrioDenseMulti = 1, kPrioListMulti = 2, kPrioSyndromeMulti = 3;
+// quantized decoder (which has no list): the later a phase is in the round,
+// the higher it runs, so that the SIMD finishes the rounds it has started
+// before it starts others (a frame of several waves meets its other waves at
+// workgroup barriers; a wave that lags behind them catches up first).
+constexpr int kPrioHead = 0, kPrioDense = 1, kPrioList = 2, kPrioSyndrome = 3;
 constexpr int kPrioPackedHead = 1, kPrioPackedDense = 2, kPrioPackedSyndrome = 3;
 
 // decode_kernel's EXT argument: which decoder family the instance holds
@@ -417,14 +415,12 @@ struct Tables {
 // the threshold table below), so a_k >= T_c implies a_k - theta_k >= |qs| *
 // bound.  Every other pair goes through the transform.
 //
-// Wave priorities (base kernel): within a round the dense draw-and-settle
-// phase runs at the highest priority, the syndrome update next, the round's
-// head (stop test, smoothing) below it and the Box-Muller list (few active
-// lanes, long transcendental chains) lowest, so that the SIMD's other waves
-// keep the vector ALU busy while a wave finishes its list (about 9% faster
-// on C1008 than equal priorities); the single-bit kernel's bound phase and
-// candidate list take the same levels.  The packed quantized decoder raises
-// its syndrome update above its dense phase instead (about 2.5%).
+// Wave priorities: the phases of a round run at rising priority in round
+// order (head, dense draw-and-settle, Box-Muller list, syndrome update), so
+// that a SIMD's waves finish the rounds they have started before starting
+// new ones; the single-bit kernel's bound phase and candidate list take the
+// same levels, and the packed quantized decoder has the same order without
+// a list.
 //
 // EXT kernels add the other decoders of the paper (EXT = kExtMulti: the
 // multi-bit rule with quantization or noise reuse; kExtSingle: Step 3a;
@@ -785,7 +781,7 @@ decode_kernel(DecodeArgs a) {
     int64_t f_prev = 0;
     const float weff = quant ? a.wq : a.w;
     for (;; ++t) {
-      if (LZ || BB) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioHead : kPrioHeadMulti);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioHead);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedHead);
       const uint32_t unsat =
           LZ ? unsat_reg
@@ -935,7 +931,7 @@ decode_kernel(DecodeArgs a) {
         // through the transform.
         auto bound_single = [&](auto quant_c) -> uint64_t {
           constexpr bool kQuant = decltype(quant_c)::value;
-          __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioDense : kPrioDenseMulti);
+          __builtin_amdgcn_s_setprio(kPrioDense);
           Words4 wq[QPL];
           float avq[QPL * 4];
           float ub = INFINITY;
@@ -1004,7 +1000,7 @@ decode_kernel(DecodeArgs a) {
               total += (uint32_t)__popcll(bal);
             }
           }
-          __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioList : kPrioListMulti);
+          __builtin_amdgcn_s_setprio(kPrioList);
           if (total) flush_single(list, lane, total, qs, kQuant, a.qc, a.qtop, n, bl);
           return bl;
         };
@@ -1050,7 +1046,7 @@ decode_kernel(DecodeArgs a) {
         // first word has c leading zeros, the float above theta_max + B_c,
         // with theta_max the largest threshold a bit can hold in round t:
         // theta_t for theta <= 0, theta itself for theta > 0
-        if (LZ) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioDense : kPrioDenseMulti);
+        if (LZ) __builtin_amdgcn_s_setprio(kPrioDense);
         const float tl = LZ ? next_up((a.theta > 0.0f ? a.theta : tht) + bcl) : 0.0f;
         const PhiloxRound pr = philox_round((uint32_t)t, fr_lo, key0, key1);
         uint32_t pend = 0;     // bit 2r+p: pair p of quad r waits in the list
@@ -1150,7 +1146,7 @@ decode_kernel(DecodeArgs a) {
             total += (uint32_t)__popcll(bal);
           }
         }
-        if (LZ) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioList : kPrioListMulti);
+        if (LZ) __builtin_amdgcn_s_setprio(kPrioList);
         if (total) drain(0u, total, pend, posb);
         if (LZ) {
           // the round's decisions of this lane's listed pairs (0 elsewhere)
@@ -1167,7 +1163,7 @@ decode_kernel(DecodeArgs a) {
           if (!((flip >> q) & 1u)) thr[q] = thr[q] * a.lambda;
       }
       xneg ^= flip;
-      if (LZ || BB) __builtin_amdgcn_s_setprio(WPF == 1 ? kPrioSyndrome : kPrioSyndromeMulti);
+      if (LZ || BB) __builtin_amdgcn_s_setprio(kPrioSyndrome);
       if (QR) __builtin_amdgcn_s_setprio(kPrioPackedSyndrome);
       if (TRACE) {
 #pragma unroll
