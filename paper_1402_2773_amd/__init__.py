@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              "`python paper_1402_2773_amd/build.py` (or __graft_entry__.build())")
+                              "`python paper_1402_2773_amd/build.py`")
         L = ctypes.CDLL(LIB_PATH)
         P, I32, I64, U32, U64, F = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                     ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float)
