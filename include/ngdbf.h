@@ -307,9 +307,11 @@ typedef struct {
  * which fills the device, run one after another on `stream` beside them.  The
  * whole batch is one node group when the caller captures `stream` into a
  * hipGraph.  Every job is validated before any work is queued.  Results equal
- * those of ngdbf_decode per job.
+ * those of ngdbf_decode per job.  Each job takes its own frame queue (see
+ * ngdbf_decode), so a batch holds at most 1024 jobs.
  * jobs: host array [n_jobs]; all codes on the current device.
- * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0), NGDBF_EDEVICE.
+ * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0 or above 1024),
+ * NGDBF_EBUSY (a job's queue still held by a launch in flight), NGDBF_EDEVICE.
  */
 ngdbf_status ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
 
