@@ -9,7 +9,10 @@ one graph-captured ngdbf_decode_batch call.  It prints one JSON line with
 decoded information Gbit/s (the value), edge updates/s, BER/FER per code, the
 same frames decoded by plain per-code launches, per-step latency, the
 dominant kernel's roofline position, the single-code headline point (C1008
-SM-NGDBF at 3.5 dB) and the CPU oracle's rate on a sample of every code.
+SM-NGDBF at 3.5 dB), the other benchmark configurations measured in the same
+run (the N=96 point, N=4000 SM-NGDBF at 3.5 dB, the high-rate N=2048 code
+with float32 and int8 samples, a short serving window) and the CPU oracle's
+rate on a sample of every code.
 
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
 """
@@ -92,6 +95,19 @@ WORKLOADS = {
 }
 HEADLINE = "c1008_sm_3.5dB"
 DEFAULT = "mix4"
+# single-code points measured beside the default batch
+EXTRA_POINTS = ["c96_plain_4dB", "c4000_sm_3.5dB", "c2048_plain_4.5dB_f32", "c2048_plain_4.5dB_i8"]
+
+
+def brief(r: dict) -> dict:
+    """The figures of a single-code run that the default line carries."""
+    keys = ("value", "unit", "ms_per_step", "edge_updates_per_s", "avg_iterations", "ber", "fer",
+            "launch_shape", "latency_ms")
+    out = {k: r[k] for k in keys if k in r}
+    out["config"] = r["config"]["description"] + f", {r['config']['frames']} frames"
+    rf = r.get("roofline") or {}
+    out["roofline"] = {k: rf.get(k) for k in ("bound", "frac", "hbm_frac", "lds_frac_method")}
+    return out
 
 # launch shapes (waves per frame, quads per lane, frames per workgroup) for
 # workloads whose default shape is slower: the (6,32) code's searched
@@ -367,6 +383,20 @@ def run_mix4(args) -> int:
     }
     if not args.no_extras:
         result["headline_c1008_sm_3.5dB"] = run_single_point(args, HEADLINE, quiet=True)
+        # the other benchmark configurations, measured in the same run: the
+        # N=96 point, the N=4000 SM-NGDBF point, the high-rate (6,32) code
+        # with float32 and int8 samples (2^21 frames each), and a short
+        # serving window (batched runtime only)
+        result["other_configs"] = {w: brief(run_single_point(args, w, quiet=True)) for w in EXTRA_POINTS}
+        # (1e4 requests/s of 1-4096 frames offer more frames than one GPU
+        # decodes; 2e3/s stays below capacity)
+        for rate in (1e4, 2e3):
+            srv = serve_measure(rate, 3.0, 4096, True)
+            result["other_configs"][f"serve_{int(rate)}_per_s_3s"] = {
+                "what": srv["config"]["description"] + f"; Poisson {int(rate)} req/s for 3 s, 1-4096 frames each",
+                "info_gbps": srv["batched"]["info_gbps"], "frames_per_s": srv["batched"]["frames_per_s"],
+                "latency_ms": srv["batched"]["latency_ms"], "served_requests": srv["batched"]["served_requests"],
+                "unserved_requests": srv["batched"]["unserved_requests"], "launches": srv["batched"]["launches"]}
     if not args.no_cpu_baseline:
         oracle_build()
         cores, model = host_cpu()
@@ -391,14 +421,22 @@ def run_mix4(args) -> int:
 
 
 def run_serve(args) -> int:
-    """Open-loop serving: Poisson request arrivals at --serve-rate req/s for
-    --serve-seconds, frames per request log-uniform in [1, --serve-max-frames], code uniform
+    """Open-loop serving (serve_measure) with the --serve-* options; one JSON line."""
+    result = serve_measure(args.serve_rate, args.serve_seconds, args.serve_max_frames,
+                           args.serve_batched_only)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def serve_measure(rate: float, seconds: float, max_frames: int, batched_only: bool) -> dict:
+    """Open-loop serving: Poisson request arrivals at `rate` req/s for
+    `seconds`, frames per request log-uniform in [1, max_frames], code uniform
     over the four codes, per-request Eb/N0 ~ U[2, 5] dB, decoder seed = request
     id.  The same arrival sequence is served twice by the native runtime:
     continuously batched (every committed request of a code joins one launch)
-    and with one launch per request.  Latency runs from a request's scheduled
-    arrival to the host seeing it finished; requests still queued when the
-    arrival window closes are reported as unserved."""
+    and with one launch per request (unless batched_only).  Latency runs from
+    a request's scheduled arrival to the host seeing it finished; requests
+    still queued when the arrival window closes are reported as unserved."""
     import numpy as np
     import torch
 
@@ -411,10 +449,10 @@ def run_serve(args) -> int:
     cl = [codes.named_code(nm) for nm in names]
     dcs = [ng.Code.from_ldpc(c) for c in cl]
     pool = [1 << 18, 1 << 18, 1 << 17, 1 << 16]  # resident slots per code (1 GiB of y at most)
-    rng = np.random.default_rng(int(args.serve_rate) + 17)
-    n_req = int(rng.poisson(args.serve_rate * args.serve_seconds))
-    t_arr = np.sort(rng.uniform(0.0, args.serve_seconds, n_req))  # Poisson process
-    mf = args.serve_max_frames
+    rng = np.random.default_rng(int(rate) + 17)
+    n_req = int(rng.poisson(rate * seconds))
+    t_arr = np.sort(rng.uniform(0.0, seconds, n_req))  # Poisson process
+    mf = max_frames
     n_fr = np.minimum(np.exp(rng.uniform(0.0, math.log(mf + 1.0), n_req)).astype(np.int64), mf)
     n_fr = np.maximum(n_fr, 1)
     code_of = rng.integers(0, len(names), n_req).astype(np.int32)
@@ -505,26 +543,25 @@ def run_serve(args) -> int:
                                "p99": float(np.percentile(lat, 99)) if len(lat) else None,
                                "p99.9": float(np.percentile(lat, 99.9)) if len(lat) else None}}
 
-    batched = serve(32768, 1, args.serve_seconds)
+    batched = serve(32768, 1, seconds)
     print(f"# batched: {batched}", file=sys.stderr, flush=True)
-    single = serve(1, 8, args.serve_seconds) if not args.serve_batched_only else None
+    single = serve(1, 8, seconds) if not batched_only else None
     result = {
         "metric": METRIC, "value": batched["info_gbps"], "unit": "Gbit/s", "n_gpus": 1,
         "steps": 1, "warmup": 0, "ms_per_step": batched["span_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic: seeded regular LDPC codes, all-zero codeword, BPSK-AWGN, Poisson arrivals",
-        "config": {"workload": "serve", "rate_req_per_s": args.serve_rate,
-                   "window_s": args.serve_seconds, "requests": n_req,
+        "config": {"workload": "serve", "rate_req_per_s": rate,
+                   "window_s": seconds, "requests": n_req,
                    "frames_per_request": f"log-uniform [1, {mf}]",
                    "offered_frames": int(n_fr.sum()), "codes": names, "pool_slots": pool,
                    "description": "continuous batching over resident slot pools, 4 codes, "
                                   "Eb/N0 ~ U[2,5] dB per request, decoder seed = request id"},
         "latency_ms": batched["latency_ms"], "batched": batched, "per_request_launch": single,
     }
-    print(json.dumps(result), flush=True)
     for d in dcs:
         d.close()
-    return 0
+    return result
 
 
 def run_latency(args) -> int:
