@@ -278,3 +278,25 @@ def test_busy_rounds_unlisted_and_full_event_list(torch_dev, name, frames, event
     unsat, events = _round_stats(c, y, r.trace, r.iters)
     assert (unsat > 64).sum() > 50, "the case must hold rounds applied without a list"
     assert ((unsat <= 64) & (events > event_list)).sum() >= 1, "the case must overflow the event list"
+
+
+# ------------------------------------------------------------- int8 samples, one wave per frame
+
+@pytest.mark.parametrize("name,frames,ebn0,params", [
+    ("C96", 800, 3.0, oracle.Params(w=0.75, theta=-0.6, lam=1.0, eta=0.9, ymax=2.5, t_max=100)),
+    ("C1008", 200, 3.0, oracle.Params(w=0.75, theta=-0.9, lam=0.99, eta=0.95, ymax=2.5, t_max=300,
+                                      smooth_window=64)),
+])
+def test_int8_samples_one_wave_per_frame(torch_dev, name, frames, ebn0, params):
+    """int8 storage (y_q = clamp(rint(16 y)), decoded as y_q / 16) through the
+    one-wave instances of the base kernel, with a share of exact zeros
+    (sign(0) = +1) and saturated samples: whole flip traces must match."""
+    c, _ = dev_code(name)
+    sig = float(np.float32(channel.sigma_from_ebn0(ebn0, c.rate)))
+    y = channel.quantize_int8(channel.bpsk_awgn(frames, c.n, sig, seed=95))
+    rng = np.random.Generator(np.random.PCG64(96))
+    y[rng.random(y.shape) < 0.02] = 0
+    y[rng.random(y.shape) < 0.01] = 127
+    assert (y == 0).mean() > 0.01
+    say(f"int8 {name} frames={frames}")
+    run_both(torch_dev, name, y, sig, params, seed=97, trace=True)
