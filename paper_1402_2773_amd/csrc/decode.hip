@@ -365,13 +365,16 @@ struct SlotPlan {
 };
 
 // Check-toggle events a frame lists per round for the parallel u update: up
-// to one per check (a round toggles each check at most once), 256 per wave of
-// the frame (events past the cap are applied by their owners, slower but
-// alike), within the exact range of the kernel's division by d_c; irregular
-// codes apply their toggles directly and list none.
+// to one per check (a round toggles each check at most once), 256 per frame
+// (events past the cap are applied by their owners, slower but alike; busy
+// rounds list nothing where the owners apply their events themselves, and a
+// small list leaves C4000's frames the LDS for five frames per CU), within
+// the exact range of the kernel's division by d_c; irregular codes apply
+// their toggles directly and list none.
 int event_cap(const ngdbf_code *c, int wpf, bool one_flip) {
+  (void)wpf;
   if (!c->dc) return 0;
-  const int cap = std::min(std::min(c->m, 256 * wpf), std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
+  const int cap = std::min(std::min(c->m, 256), std::min(4095, ((1 << 20) - 1) / (c->dc * c->dc)));
   return one_flip ? std::min(cap, 16) : cap;  // one flip toggles at most d_v <= 15 checks
 }
 

@@ -433,12 +433,15 @@ struct Tables {
 // integer) and the noise chain of Sec. V-B (the frame's n + T - 1 samples are
 // drawn once into LDS; bit k reads element n - 1 + t - k in round t).
 
-// Occupancy target: four waves per SIMD; the base kernel with four or more
-// waves per frame (code tables outside the LDS, as for two) aims higher when
-// each lane holds fewer quads.
+// Occupancy target: four waves per SIMD; the base kernel with two or more
+// waves per frame (code tables read through the caches) aims higher, and
+// more so when each lane holds fewer quads: five waves at four quads per
+// lane (a few registers spill, but the extra wave hides more of the table
+// reads: C4000 at (4,4) 396 -> 357 ms, C2048 at (2,4) 199 -> 190 ms on a
+// mixed-SNR batch), six at two quads, eight at one.
 template <int WPF, int QPL, int EXT>
 constexpr int waves_per_simd() {
-  return (EXT == kExtNone && WPF >= 4) ? (QPL == 1 ? 8 : (QPL == 2 ? 6 : 4)) : 4;
+  return (EXT == kExtNone && WPF >= 2) ? (QPL == 1 ? 8 : (QPL == 2 ? 6 : 5)) : 4;
 }
 
 template <int WPF, int QPL, int YFMT, bool TRACE, bool REG, int EXT>
