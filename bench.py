@@ -30,17 +30,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "decoded info Gbit/s + edge-updates/s on 1 MI355X at fixed BER; p50/p99 decode latency"
 
-# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A wave64 vector-ALU instruction holds
-# its SIMD for ISSUE_CYCLES[class] clocks (measured by --workload issue-rates:
-# four for 32/64-bit integer, bitwise, shift and conversion instructions, two
-# for binary32 fma/mul/add, eight for transcendentals).  The issue ceiling is
-# counted in 4-clock slots of 64 lanes: 256 x 4 x 2.4e9 / 4 x 64 = 39.32e12
-# lane-op slots/s (an fp32 fma fills half a slot).
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz.  A SIMD issues vector-ALU work in
+# 4-clock slots of 64 lanes: one wave64 instruction per slot, or two in one
+# slot when both are of the dual-issue kinds (binary32 fma / mul / add and the
+# VOP2 forms of mov, and, or, xor, add_u32, lshrrev), and a transcendental
+# takes two slots (measured by --workload issue-rates).  The issue ceiling is
+# 256 x 4 x 2.4e9 / 4 slots x 64 lanes = 39.32e12 lane slots/s; a launch fills
+# SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2 of them (slots any VALU
+# instruction was issued in, less those holding a second one).
 PEAK_ISSUE_TSLOTS = 256 * 4 * 2.4e9 / 4 * 64 / 1e12
 PEAK_HBM_GBS = 8000.0
-ISSUE_CYCLES = {"SQ_INSTS_VALU_INT32": 4, "SQ_INSTS_VALU_INT64": 4, "SQ_INSTS_VALU_CVT": 4,
-                "SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_MUL_F32": 2, "SQ_INSTS_VALU_ADD_F32": 2,
-                "SQ_INSTS_VALU_TRANS_F32": 8, "other": 4}
 # LDS ceiling of the method's on-chip exchange (one bank access per edge
 # gather, 2 nnz gathers per frame-round, no bit slicing): 256 CUs x 32 banks
 # x 2.4 GHz of bank accesses; bit-iterations/s = that / (2 d_v)
@@ -151,19 +150,21 @@ def counter_profile(workload: str):
     return d
 
 
-def issue_slots(counters: dict) -> float:
-    """4-clock vector-ALU issue slots a launch fills: every instruction class
-    counted by its SQ counter, weighted by its issue time."""
-    classes = [k for k in ISSUE_CYCLES if k != "other"]
-    other = counters["SQ_INSTS_VALU"] - sum(counters.get(k, 0.0) for k in classes)
-    return (sum(counters.get(k, 0.0) * ISSUE_CYCLES[k] for k in classes) + other * ISSUE_CYCLES["other"]) / 4.0
+def issue_slots(counters: dict):
+    """4-clock vector-ALU issue slots a launch filled (each SIMD's slots with
+    at least one VALU instruction issued, summed), or None without the issue
+    counters."""
+    if "SQ_ACTIVE_INST_VALU" not in counters or "SQ_ACTIVE_INST_VALU2" not in counters:
+        return None
+    return counters["SQ_ACTIVE_INST_VALU"] - counters["SQ_ACTIVE_INST_VALU2"]
 
 
 def roofline(code, frames: int, yfmt: str, kernel_ms: float, bit_iters: float, counters,
              per_frame_sigma: bool, kernel: str) -> dict:
     """The kernel's position against the vector-ALU issue ceiling (the bound:
-    every decode kernel here issues on nearly every SIMD clock), with the HBM
-    and LDS fractions of the method's algorithmic traffic beside it."""
+    a large decode launch issues in 0.8-0.9 of the SIMDs' issue slots, while
+    HBM and LDS stay far below theirs), with the HBM and LDS fractions of the
+    method's algorithmic traffic beside it."""
     ks = kernel_ms / 1e3
     alg_bytes = frames * hbm_bytes_per_frame(code, yfmt, per_frame_sigma)
     dv = code.nnz / code.n
@@ -179,8 +180,10 @@ def roofline(code, frames: int, yfmt: str, kernel_ms: float, bit_iters: float, c
                      "2 nnz edge gathers per frame-round at one bank access each"}
     if counters:
         slots = issue_slots(counters)
-        r["achieved"] = slots * 64 / ks / 1e12
-        r["frac"] = r["achieved"] / PEAK_ISSUE_TSLOTS
+        if slots is not None:
+            r["achieved"] = slots * 64 / ks / 1e12
+            r["frac"] = r["achieved"] / PEAK_ISSUE_TSLOTS
+            r["dual_issued_fraction"] = 2 * counters["SQ_ACTIVE_INST_VALU2"] / counters["SQ_INSTS_VALU"]
         r["executed_valu_lane_ops_per_s"] = counters["SQ_INSTS_VALU"] * 64 / ks
         r["valu_instructions_per_launch"] = counters["SQ_INSTS_VALU"]
         if counters.get("traffic_bytes") is not None:
@@ -767,6 +770,16 @@ def run_phases(args) -> int:
     return 0
 
 
+# the issue probe's kinds: one instruction per chain step (kind 1: two)
+ISSUE_PROBE_KINDS = [
+    "int32 (v_xad_u32)", "int64 product + xor (v_mad_u64_u32, v_xor_b32)", "fp32 fma (v_fmamk_f32)",
+    "fp32 mul", "fp32 sqrt (transcendental)", "v_xor_b32", "v_lshlrev_b32", "v_mad_u64_u32",
+    "v_bitop3_b32", "v_and_b32", "v_or_b32", "v_mov_b32", "v_cndmask_b32 (VOP3)", "v_add_u32",
+    "v_lshrrev_b32", "v_bfe_u32", "v_cmp_eq_u32 (VOP3)", "v_cmp_lt_f32 (VOP3)", "v_readlane_b32",
+    "v_writelane_b32", "v_mbcnt_lo_u32_b32", "v_ffbh_u32", "v_lshl_add_u64", "v_add3_u32",
+    "v_mad_u32_u24", "v_lshl_add_u32", "v_or3_b32", "v_mul_u32_u24"]
+
+
 def run_issue_rates(args) -> int:
     """Clocks a wave64 vector-ALU instruction of each class holds its SIMD:
     the library's issue probe (long unrolled chains of one class) at eight
@@ -779,17 +792,17 @@ def run_issue_rates(args) -> int:
     blocks, iters = cus * 8, 2000
     out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-    names = ["int32 (v_xad_u32)", "int64 product + xor (v_mad_u64_u32, v_xor_b32)", "fp32 fma",
-             "fp32 mul", "fp32 sqrt (transcendental)"]
-    per_step = [1, 2, 1, 1, 1]
+    names = ISSUE_PROBE_KINDS
+    per_step = [2 if k == 1 else 1 for k in range(len(names))]
+    kinds = [int(k) for k in args.probe_kinds.split(",")] if args.probe_kinds else range(len(names))
     rows = []
-    for kind in range(5):
+    for kind in kinds:
         def one(kind=kind):
             ng.ngdbf_issue_probe(kind, blocks, iters, out, stream)
         _, ms = timed_steps(torch, one, 3, 1, stream)
         steps_per_simd = blocks * 4 * iters * 16 * 8 / (cus * 4.0)
         cyc = min(ms) * 1e-3 * 2.4e9 / steps_per_simd / per_step[kind]
-        rows.append({"class": names[kind], "ms": min(ms), "clocks_per_wave64_instruction": cyc})
+        rows.append({"kind": kind, "class": names[kind], "ms": min(ms), "clocks_per_wave64_instruction": cyc})
         print(f"# {rows[-1]}", file=sys.stderr, flush=True)
     print(json.dumps({"workload": "issue-rates", "cus": cus, "clock_ghz_assumed": 2.4,
                       "waves_per_simd": 8, "rows": rows}), flush=True)
@@ -819,6 +832,7 @@ def main() -> int:
     ap.add_argument("--serve-max-frames", type=int, default=4096,
                     help="serve: frames per request are log-uniform in [1, this]")
     ap.add_argument("--serve-batched-only", action="store_true")
+    ap.add_argument("--probe-kinds", default="", help="issue-rates: comma-separated probe kinds (default all)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this size (for HBM counter scaling)")
     args = ap.parse_args()

@@ -500,8 +500,14 @@ ngdbf_status ngdbf_frame_stats(int32_t n, int64_t n_frames, const uint8_t *bits,
  * issue; the benchmark weights each class's hardware counter by this time).
  *   kind   : 0 32-bit integer (v_xad_u32), 1 64-bit product plus xor
  *            (v_mad_u64_u32, v_xor_b32), 2 binary32 fma, 3 binary32 multiply,
- *            4 transcendental (v_sqrt_f32); every chain step is one
- *            instruction (kind 1: two).
+ *            4 transcendental (v_sqrt_f32), 5..27 one instruction each:
+ *            v_xor_b32, v_lshlrev_b32, v_mad_u64_u32, v_bitop3_b32,
+ *            v_and_b32, v_or_b32, v_mov_b32, v_cndmask_b32, v_add_u32,
+ *            v_lshrrev_b32, v_bfe_u32, v_cmp_eq_u32, v_cmp_lt_f32,
+ *            v_readlane_b32, v_writelane_b32, v_mbcnt_lo_u32_b32,
+ *            v_ffbh_u32, v_lshl_add_u64, v_add3_u32, v_mad_u32_u24,
+ *            v_lshl_add_u32, v_or3_b32, v_mul_u32_u24; every chain step is
+ *            one instruction (kind 1: two).
  *   blocks : workgroups of 256 threads; iters >= 1 outer iterations of 16 x 8
  *            chain steps per thread.
  *   out    : dev uint32 [blocks * 256], receives a value per thread.

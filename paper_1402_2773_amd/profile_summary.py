@@ -2,11 +2,13 @@
 profile that bench.py reads (profiles/counters_<workload>.json).
 
   python -m paper_1402_2773_amd.profile_summary --workload mix4 \\
-      --classes CLS.csv --fetch FETCH.csv --write WRITE.csv --trace STATS.csv [--lds LDS.csv]
+      --classes CLS.csv --issue ISSUE.csv --fetch FETCH.csv --write WRITE.csv \\
+      --trace STATS.csv [--lds LDS.csv]
 
 Inputs are rocprofv3 ``*_counter_collection.csv`` files (one run per counter
-set: the vector-ALU instruction classes, FETCH_SIZE, WRITE_SIZE, optionally
-the LDS counters) and the ``*_kernel_stats.csv`` of a kernel-trace run.
+set: the vector-ALU instruction classes, the issue counters, FETCH_SIZE,
+WRITE_SIZE, optionally the LDS counters) and the ``*_kernel_stats.csv`` of a
+kernel-trace run.
 Every dispatch of one decode-kernel instance in such a run decodes the same
 frames, so the median over its dispatches is its per-launch figure.  HBM
 bytes are scaled by what the same counter reads for the plain 1 GiB device
@@ -74,6 +76,7 @@ def main(argv=None) -> int:
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--trace")
+    ap.add_argument("--issue", help="counter CSV of the issue pass (SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_VALU2)")
     ap.add_argument("--lds")
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--commands", default="", help="JSON object of the commands that made the inputs")
@@ -105,6 +108,14 @@ def main(argv=None) -> int:
             if code in fi and code in wi and fs and ws:
                 fb, wb = fi[code]["FETCH_SIZE"] * fs, wi[code]["WRITE_SIZE"] * ws
                 result["instances"][code].update(fetch_bytes=fb, write_bytes=wb, traffic_bytes=fb + wb)
+    if args.issue:
+        ii, _ = per_instance(args.issue, codes)
+        for code in result["instances"]:
+            if code in ii:
+                for k, v in ii[code].items():
+                    if k.startswith("SQ_ACTIVE_INST") or k == "SQ_BUSY_CYCLES":
+                        result["instances"][code][k] = v
+                result["instances"][code]["GRBM_GUI_ACTIVE_issue_pass"] = ii[code].get("GRBM_GUI_ACTIVE")
     if args.lds:
         li, _ = per_instance(args.lds, codes)
         for code in result["instances"]:

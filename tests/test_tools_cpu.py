@@ -75,8 +75,11 @@ def test_profile_summary_medians_and_copy_scaling(tmp_path):
                             (2, k14, "FETCH_SIZE", 100.0), (3, k44, "FETCH_SIZE", 10.0)])
     _write_counters(write, [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0),
                             (2, k14, "WRITE_SIZE", 50.0), (3, k44, "WRITE_SIZE", 5.0)])
+    iss = tmp_path / "i.csv"
+    _write_counters(iss, [(1, k14, "SQ_ACTIVE_INST_VALU", 21), (1, k14, "SQ_ACTIVE_INST_VALU2", 5),
+                          (1, k14, "GRBM_GUI_ACTIVE", 8)])
     out = subprocess.run([sys.executable, "-m", "paper_1402_2773_amd.profile_summary", "--workload", "mix4",
-                          "--classes", str(cls), "--fetch", str(fetch), "--write", str(write),
+                          "--classes", str(cls), "--issue", str(iss), "--fetch", str(fetch), "--write", str(write),
                           "--copy-bytes", "1024"], cwd=ROOT, capture_output=True, text=True, check=True)
     d = json.loads(out.stdout)
     assert d["kernel_sources_sha256"] == bench.kernel_sources_digest()
@@ -88,25 +91,29 @@ def test_profile_summary_medians_and_copy_scaling(tmp_path):
     assert d["copy_calibration"]["write_bytes_per_unit"] == 1.0
     assert (c1008["fetch_bytes"], c1008["write_bytes"], c1008["traffic_bytes"]) == (200.0, 50.0, 250.0)
     assert c4000["traffic_bytes"] == 25.0
+    assert (c1008["SQ_ACTIVE_INST_VALU"], c1008["SQ_ACTIVE_INST_VALU2"]) == (21, 5)
+    assert "SQ_ACTIVE_INST_VALU" not in c4000
     assert "C96" not in d["instances"]
 
 
-def test_issue_slots_weigh_each_class_by_its_clocks():
-    c = {"SQ_INSTS_VALU": 100.0, "SQ_INSTS_VALU_INT32": 40.0, "SQ_INSTS_VALU_FMA_F32": 20.0,
-         "SQ_INSTS_VALU_TRANS_F32": 10.0}
-    # 40 x 4 + 20 x 2 + 10 x 8 + (100 - 70 unclassified) x 4 clocks, in 4-clock slots
-    assert bench.issue_slots(c) == pytest.approx(100.0)
+def test_issue_slots_count_dual_issued_pairs_once():
+    # 100 instructions issued, 30 of the 4-clock slots held two of them
+    c = {"SQ_INSTS_VALU": 100.0, "SQ_ACTIVE_INST_VALU": 100.0, "SQ_ACTIVE_INST_VALU2": 30.0}
+    assert bench.issue_slots(c) == pytest.approx(70.0)
+    assert bench.issue_slots({"SQ_INSTS_VALU": 100.0}) is None
     assert bench.PEAK_ISSUE_TSLOTS == pytest.approx(256 * 4 * 2.4e9 / 4 * 64 / 1e12)
 
 
 def test_roofline_fractions():
     code = codes.named_code("C1008")
     frames, ms = 1000, 2.0
-    c = {"SQ_INSTS_VALU": 1e9, "SQ_INSTS_VALU_FMA_F32": 5e8, "traffic_bytes": 5e6, "source": "test"}
+    c = {"SQ_INSTS_VALU": 1e9, "SQ_ACTIVE_INST_VALU": 1.01e9, "SQ_ACTIVE_INST_VALU2": 2.5e8,
+         "traffic_bytes": 5e6, "source": "test"}
     r = bench.roofline(code, frames, "f32", ms, 1e9, c, False, "k")
-    slots = (5e8 * 2 + 5e8 * 4) / 4.0
+    slots = 1.01e9 - 2.5e8
     assert r["achieved"] == pytest.approx(slots * 64 / 2e-3 / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"])
+    assert r["dual_issued_fraction"] == pytest.approx(0.5)
     per_frame = 4 * code.n + (code.n + 7) // 8 + 4 + 1
     assert r["algorithmic_bytes"] == frames * per_frame
     assert r["hbm_frac"] == pytest.approx(frames * per_frame / 2e-3 / 8e12)
