@@ -96,7 +96,8 @@ def main(argv=None) -> int:
               "instances": {}}
     for code, cs in inst.items():
         result["instances"][code] = {k: v for k, v in cs.items() if k.startswith("SQ_") or k.startswith("GRBM")}
-        result["instances"][code]["source"] = "rocprofv3 SQ_INSTS_VALU* counters, median per launch"
+        result["instances"][code]["source"] = ("rocprofv3 SQ counters (VALU instruction classes; issue slots "
+                                               "SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_VALU2), median per launch")
     if args.fetch and args.write:
         fs, fraw = copy_scale(args.fetch, "FETCH_SIZE", args.copy_bytes)
         ws, wraw = copy_scale(args.write, "WRITE_SIZE", args.copy_bytes)
