@@ -68,6 +68,15 @@ def test_noise_probe_rejects_bad_ranges(L):
         ng.ngdbf_noise_probe(1, (1 << 24) - 1, 2, 0, 0, 0, buf, buf, 0)
 
 
+def test_issue_probe_rejects_bad_arguments(L):
+    # every check happens before anything touches a device
+    buf = np.zeros(256, dtype=np.uint32)
+    for kind, blocks, iters, out in [(-1, 1, 1, buf), (28, 1, 1, buf), (0, 0, 1, buf), (0, 1, 0, buf),
+                                     (0, 1, 1, None)]:
+        st = L.ngdbf_issue_probe(kind, blocks, iters, out.ctypes.data if out is not None else None, None)
+        assert st == ng.NGDBF_EINVAL
+
+
 def test_params_struct_layout_matches_header():
     assert ctypes.sizeof(ng.ngdbf_params) == 44
     names = [f[0] for f in ng.ngdbf_params._fields_]
