@@ -391,6 +391,12 @@ def run_mix4(args) -> int:
         # with float32 and int8 samples (2^21 frames each), and a short
         # serving window (batched runtime only)
         result["other_configs"] = {w: brief(run_single_point(args, w, quiet=True)) for w in EXTRA_POINTS}
+        # a parameter-search step as one batch against the same jobs launched
+        # one after another
+        g = grid_measure(8192, 3, 1)
+        result["other_configs"]["grid_c2048_27x8192"] = {
+            k: g[k] for k in ("what", "batched_ms", "sequential_ms", "speedup", "batched_info_gbps",
+                              "same_results")}
         # (1e4 requests/s of 1-4096 frames offer more frames than one GPU
         # decodes; 2e3/s stays below capacity)
         for rate in (1e4, 2e3):
@@ -770,6 +776,64 @@ def run_phases(args) -> int:
     return 0
 
 
+def run_grid(args) -> int:
+    r = grid_measure(args.frames or 8192, args.steps, args.warmup)
+    print(json.dumps(r), flush=True)
+    return 0 if r["same_results"] else 1
+
+
+def grid_measure(frames: int, steps: int, warmup: int) -> dict:
+    """A parameter-search step as one batch: the (6,32) C2048 code at 4.5 dB,
+    27 parameter sets (w, theta, eta each at the searched value and one step
+    either side, Sec. IV-A's successive approximation) on the same received
+    frames (8192 by default).  The batch runs its jobs concurrently on library
+    streams; the same jobs as plain launches run one after another on one
+    stream.  Both timed with HIP events; results compared job by job."""
+    import numpy as np
+    import torch
+
+    import paper_1402_2773_amd as ng
+    from paper_1402_2773_amd import sweep
+    from synth import channel, codes
+
+    c = codes.named_code("C2048")
+    base = sweep.high_rate_tuned_params(4.5)
+    sets = [dict(base, w=w, theta=th, eta=eta) for w in (0.14, 0.162, 0.184)
+            for th in (-0.25, -0.287, -0.324) for eta in (0.57, 0.613, 0.656)]
+    sig = float(np.float32(channel.sigma_from_ebn0(4.5, c.rate)))
+    y = ng.channel(c.n, frames, sig, seed=sweep.channel_seed(2048))
+    dc = ng.Code.from_ldpc(c)
+    ps = [ng.Params(**pr) for pr in sets]
+    outs_b = [ng.alloc_outputs(dc, frames, "cuda") for _ in sets]
+    outs_s = [ng.alloc_outputs(dc, frames, "cuda") for _ in sets]
+    jobs = [ng.job(dc, y, sig, p, 7, o) for p, o in zip(ps, outs_b)]
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        ng.ngdbf_decode_batch(jobs, stream)
+
+    def sequential():
+        for p, o in zip(ps, outs_s):
+            ng.decode(dc, y, sig, p, 7, out=o, stream=stream)
+
+    _, b_ms = timed_steps(torch, batched, steps, warmup, stream)
+    _, s_ms = timed_steps(torch, sequential, steps, warmup, stream)
+    same = all(torch.equal(a.bits, b.bits) and torch.equal(a.iters, b.iters) and
+               torch.equal(a.converged, b.converged) for a, b in zip(outs_b, outs_s))
+    bm, sm = min(b_ms), min(s_ms)
+    info = len(sets) * frames * c.k_info
+    r = {
+        "workload": "grid", "what": "27 parameter sets of the (6,32) C2048 code at 4.5 dB on the same "
+                                    f"{frames} frames (w, theta, eta around the searched set)",
+        "jobs": len(sets), "frames_per_job": frames,
+        "shape": list(ng.ngdbf_code_get_shape(dc.handle, ps[0].c(ng.NGDBF_Y_F32))),
+        "batched_ms": bm, "sequential_ms": sm, "speedup": sm / bm,
+        "batched_info_gbps": info / (bm / 1e3) / 1e9, "sequential_info_gbps": info / (sm / 1e3) / 1e9,
+        "batched_ms_all": b_ms, "sequential_ms_all": s_ms, "same_results": same}
+    dc.close()
+    return r
+
+
 # the issue probe's kinds: one instruction per chain step (kind 1: two)
 ISSUE_PROBE_KINDS = [
     "int32 (v_xad_u32)", "int64 product + xor (v_mad_u64_u32, v_xor_b32)", "fp32 fma (v_fmamk_f32)",
@@ -815,7 +879,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT,
-                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency", "issue-rates", "phases"])
+                    choices=sorted(WORKLOADS) + ["mix4", "serve", "latency", "issue-rates", "phases",
+                                                 "grid"])
     ap.add_argument("--frames", type=int, default=0, help="override the batch size")
     ap.add_argument("--ebn0", type=float, default=None,
                     help="phases: Eb/N0 (dB) of the C1008 SM-NGDBF point (default the headline's)")
@@ -865,6 +930,8 @@ def main() -> int:
         return run_issue_rates(args)
     if args.workload == "phases":
         return run_phases(args)
+    if args.workload == "grid":
+        return run_grid(args)
     print(json.dumps(run_single_point(args, args.workload)), flush=True)
     return 0
 
