@@ -32,7 +32,7 @@ def torch_dev():
 
 
 def heur(ebn0):
-    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.5 else 0.90
+    lam = 0.99 if ebn0 < 3.5 else 0.97 if ebn0 < 4.0 else 0.94 if ebn0 < 4.25 else 0.90
     return oracle.Params(w=0.75, theta=-0.9, lam=lam, eta=0.95, ymax=2.5, t_max=300, smooth_window=64)
 
 
@@ -171,6 +171,35 @@ def test_batch_equals_oracle(torch_dev):
         same(host(it["out"]), r)
     for it in items:
         it["dc"].close()
+
+
+def test_batch_of_many_parameter_sets(torch_dev):
+    """A parameter-search step: 27 parameter sets on one code and the same
+    received frames, all concurrent on the library's streams (jobs below the
+    full-device size), equal to one-at-a-time decodes and, on sampled jobs
+    and frames, to the oracle."""
+    torch = torch_dev
+    c = codes.named_code("C1008")
+    dc = ng.Code.from_ldpc(c)
+    F = 384
+    sig = float(np.float32(channel.sigma_from_ebn0(3.0, c.rate)))
+    y = channel.bpsk_awgn_device(F, c.n, sig, seed=411)
+    base = heur(3.0)
+    sets = [oracle.Params(**dict(base.__dict__, w=w, theta=th, eta=eta))
+            for w in (0.6, 0.75, 0.9) for th in (-0.7, -0.9, -1.1) for eta in (0.85, 0.95, 1.05)]
+    outs = [ng.alloc_outputs(dc, F, "cuda") for _ in sets]
+    jobs = [ng.job(dc, y, sig, ng.Params(**p.__dict__), 500 + i, o) for i, (p, o) in enumerate(zip(sets, outs))]
+    say("batch of", len(jobs), "parameter sets")
+    ng.ngdbf_decode_batch(jobs, None)
+    torch.cuda.synchronize()
+    for i, (p, o) in enumerate(zip(sets, outs)):
+        r = ng.decode(dc, y, sig, ng.Params(**p.__dict__), 500 + i)
+        assert torch.equal(o.bits, r.bits) and torch.equal(o.iters, r.iters) and torch.equal(o.converged, r.converged)
+    yh = y[:24].cpu().numpy()
+    for i in (0, 13, 26):
+        r = oracle.decode(c, yh, sig, sets[i], 500 + i, threads=8)
+        same(host(ng.Outputs(outs[i].bits[:24], outs[i].iters[:24], outs[i].converged[:24])), r)
+    dc.close()
 
 
 def test_batch_graph_replays(torch_dev):
