@@ -105,7 +105,7 @@ def brief(r: dict) -> dict:
     out = {k: r[k] for k in keys if k in r}
     out["config"] = r["config"]["description"] + f", {r['config']['frames']} frames"
     rf = r.get("roofline") or {}
-    out["roofline"] = {k: rf.get(k) for k in ("bound", "frac", "hbm_frac", "lds_frac_method")}
+    out["roofline"] = {k: rf.get(k) for k in ("bound", "frac", "hbm_frac", "lds_busy_frac", "lds_method_ratio")}
     return out
 
 # launch shapes (waves per frame, quads per lane, frames per workgroup) for
@@ -175,9 +175,14 @@ def roofline(code, frames: int, yfmt: str, kernel_ms: float, bit_iters: float, c
          "traffic_unit": "bytes/launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
          "algorithmic_bytes": alg_bytes, "hbm_achieved_GBs": alg_bytes / ks / 1e9,
          "hbm_frac": alg_bytes / ks / 1e9 / PEAK_HBM_GBS,
-         "lds_frac_method": bit_iters / ks / lds_ceiling_bit_iters,
-         "lds_what": "bit-iterations/s against 256 CUs x 32 banks x 2.4 GHz / (2 d_v): the method's "
-                     "2 nnz edge gathers per frame-round at one bank access each"}
+         "lds_method_ratio": bit_iters / ks / lds_ceiling_bit_iters,
+         "lds_method_what": "bit-iterations/s against 256 CUs x 32 banks x 2.4 GHz / (2 d_v), the "
+                            "ceiling of the method's 2 nnz edge gathers per frame-round at one bank "
+                            "access each; not executed work (the incremental syndrome update makes far "
+                            "fewer LDS accesses), so it can exceed 1",
+         "lds_busy_frac": None,
+         "lds_busy_what": "SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE x 32 CUs per XCD): the fraction of "
+                          "the CUs' clocks in which the LDS was busy (committed profile), at most 1"}
     if counters:
         slots = issue_slots(counters)
         if slots is not None:
@@ -188,6 +193,9 @@ def roofline(code, frames: int, yfmt: str, kernel_ms: float, bit_iters: float, c
         r["valu_instructions_per_launch"] = counters["SQ_INSTS_VALU"]
         if counters.get("traffic_bytes") is not None:
             r["traffic"] = counters["traffic_bytes"]
+        lds = counters.get("lds") or {}
+        if lds.get("SQ_LDS_IDX_ACTIVE") and lds.get("GRBM_GUI_ACTIVE"):
+            r["lds_busy_frac"] = lds["SQ_LDS_IDX_ACTIVE"] / (lds["GRBM_GUI_ACTIVE"] * 32)
         r["counters_from"] = counters.get("source")
     return r
 
@@ -311,12 +319,22 @@ def run_mix4(args) -> int:
                           out_plain=ng.alloc_outputs(dc, frames, "cuda")))
     torch.cuda.synchronize()
 
-    # batched: one batch call captured into a graph (default shapes, or the
-    # autotuner's choice on a sample with --mix-autotune)
+    # batched: one batch call captured into a graph, each code at the launch
+    # shape the autotuner picks on a sample of its own frames (or at the
+    # library's default shapes with --no-mix-autotune)
+    autotune_ms = {}
+    fixed = {}  # --mix-shapes C96=1,1,4:C1008=1,4,16 (counter runs: no tuning launches)
+    for spec in filter(None, args.mix_shapes.split(":")):
+        name, sh = spec.split("=")
+        fixed[name] = tuple(int(v) for v in sh.split(","))
     for it in items:
-        if args.mix_autotune:
+        if it["name"] in fixed:
+            ng.ngdbf_code_set_shape(it["dc"].handle, *fixed[it["name"]])
+        elif not args.no_mix_autotune:
             n_s = min(it["frames"], 1 << 17)  # several times the resident frames
+            t0 = time.perf_counter()
             ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
+            autotune_ms[it["name"]] = {"sample_frames": n_s, "wall_ms": (time.perf_counter() - t0) * 1e3}
         it["shape"] = list(ng.ngdbf_code_get_shape(it["dc"].handle, it["p"].c(ng.NGDBF_Y_F32)))
     jobs = [ng.job(it["dc"], it["y"], it["sig"], it["p"], it["seed"], it["out"]) for it in items]
     ng.ngdbf_decode_batch(jobs, None)
@@ -357,7 +375,12 @@ def run_mix4(args) -> int:
         per_code[it["name"]] = {**st, "n": it["c"].n, "k": it["c"].k_info, "nnz": it["c"].nnz,
                                 "params": it["params"], "shape": it["shape"], "kernel_ms": ms,
                                 "info_gbps_plain": it["frames"] * it["c"].k_info / (ms / 1e3) / 1e9,
-                                "issue_frac": rf["frac"], "hbm_frac": rf["hbm_frac"]}
+                                "issue_frac": rf["frac"], "hbm_frac": rf["hbm_frac"],
+                                "lds_busy_frac": rf["lds_busy_frac"]}
+        if cnt and cnt.get("workgroup_size"):
+            # the counters are per kernel instance; frames per workgroup may differ
+            per_code[it["name"]]["profiled_workgroup_size"] = int(cnt["workgroup_size"])
+            per_code[it["name"]]["workgroup_size"] = 64 * it["shape"][0] * it["shape"][2]
         it["roofline"] = rf
     dominant = max(items, key=lambda it: per_code_ms[it["name"]])
     value = info_bits / (batch_ms / 1e3) / 1e9
@@ -372,7 +395,13 @@ def run_mix4(args) -> int:
                    "ebn0_db": "per frame U[2,5]",
                    "description": "one graph-captured ngdbf_decode_batch of C96:C1008:C2048:C4000 = "
                                   "4:2:1:1 (2^22 frames), per-code parameters (Sec. IV-A)",
-                   "autotuned": bool(args.mix_autotune)},
+                   "autotuned": not args.no_mix_autotune and not fixed,
+                   "fixed_shapes": {k: list(v) for k, v in fixed.items()} or None,
+                   "autotune": ({"per_code": autotune_ms,
+                                 "what": "ngdbf_autotune times every built launch shape (waves per "
+                                         "frame, quads per lane, frames per workgroup) that fits the "
+                                         "code on the sample and keeps the fastest; untimed"}
+                                if autotune_ms else None)},
         "edge_updates_per_s": total_edges / (batch_ms / 1e3),
         "bit_iterations_per_s": total_bit_iters / (batch_ms / 1e3),
         "avg_iterations": total_iters / sum(it["frames"] for it in items),
@@ -891,7 +920,10 @@ def main() -> int:
                     help="mix4: skip the single-code headline point (profiling runs)")
     ap.add_argument("--no-draw-stats", action="store_true",
                     help="skip the extra decode that counts the Gaussian draws (profiling runs)")
-    ap.add_argument("--mix-autotune", action="store_true", help="mix4: autotune each code first")
+    ap.add_argument("--mix-shapes", default="",
+                    help="mix4: fix launch shapes instead of autotuning, e.g. C96=1,1,4:C1008=1,4,16")
+    ap.add_argument("--no-mix-autotune", action="store_true",
+                    help="mix4: run every code at the library's default shape instead of autotuning it first")
     ap.add_argument("--serve-rate", type=float, default=1e4, help="serve: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="serve: arrival window")
     ap.add_argument("--serve-max-frames", type=int, default=4096,

@@ -38,7 +38,8 @@ def dispatches(path):
     out = collections.OrderedDict()
     with open(path) as f:
         for r in csv.DictReader(f):
-            d = out.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"]})
+            d = out.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"],
+                                                       "workgroup_size": r.get("Workgroup_Size")})
             d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     return out
 
@@ -56,7 +57,10 @@ def per_instance(path, codes):
         if key is None or key not in codes:
             continue
         for k, v in d.items():
-            if k != "kernel":
+            if k == "workgroup_size":
+                if v not in (None, ""):
+                    vals[codes[key]][k].append(int(float(v)))
+            elif k != "kernel":
                 vals[codes[key]][k].append(v)
     return {code: {k: statistics.median(v) for k, v in cs.items()} for code, cs in vals.items()}, vals
 
@@ -96,6 +100,8 @@ def main(argv=None) -> int:
               "instances": {}}
     for code, cs in inst.items():
         result["instances"][code] = {k: v for k, v in cs.items() if k.startswith("SQ_") or k.startswith("GRBM")}
+        if "workgroup_size" in cs:  # threads per workgroup of the profiled launches
+            result["instances"][code]["workgroup_size"] = int(cs["workgroup_size"])
         result["instances"][code]["source"] = ("rocprofv3 SQ counters (VALU instruction classes; issue slots "
                                                "SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_VALU2), median per launch")
     if args.fetch and args.write:

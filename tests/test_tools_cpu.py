@@ -53,8 +53,9 @@ def test_isa_blocks_counts_each_block(tmp_path):
 def _write_counters(path, rows):
     with open(path, "w", newline="") as fh:
         w = csv.writer(fh)
-        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
-        w.writerows(rows)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Workgroup_Size", "Counter_Name", "Counter_Value"])
+        # rocprofv3 names each dispatch's threads per workgroup in its rows
+        w.writerows([(d, k, 1024 if "<1, 4," in k else 256, c, v) for d, k, c, v in rows])
 
 
 def test_profile_summary_medians_and_copy_scaling(tmp_path):
@@ -94,6 +95,7 @@ def test_profile_summary_medians_and_copy_scaling(tmp_path):
     assert (c1008["SQ_ACTIVE_INST_VALU"], c1008["SQ_ACTIVE_INST_VALU2"]) == (21, 5)
     assert "SQ_ACTIVE_INST_VALU" not in c4000
     assert "C96" not in d["instances"]
+    assert c1008["workgroup_size"] == 1024 and c4000["workgroup_size"] == 256
 
 
 def test_issue_slots_count_dual_issued_pairs_once():
@@ -118,6 +120,15 @@ def test_roofline_fractions():
     assert r["algorithmic_bytes"] == frames * per_frame
     assert r["hbm_frac"] == pytest.approx(frames * per_frame / 2e-3 / 8e12)
     assert r["traffic"] == 5e6 and r["bound"] == "alu"
+    # the method's LDS ratio: bit-iterations/s against 256 CUs x 32 banks x
+    # 2.4 GHz / (2 d_v); no LDS counters, no busy fraction
+    assert r["lds_method_ratio"] == pytest.approx(1e9 / 2e-3 / (256 * 32 * 2.4e9 / 6))
+    assert r["lds_busy_frac"] is None
+    # LDS busy: SQ_LDS_IDX_ACTIVE over GRBM_GUI_ACTIVE x 32 CUs per XCD
+    rl = bench.roofline(code, frames, "f32", ms, 1e9,
+                        {**c, "lds": {"SQ_LDS_IDX_ACTIVE": 16.0, "GRBM_GUI_ACTIVE": 2.0}}, False, "k")
+    assert rl["lds_busy_frac"] == pytest.approx(0.25)
     # without a profile of the current kernel the counter figures are null
     r0 = bench.roofline(code, frames, "f32", ms, 1e9, None, False, "k")
     assert r0["frac"] is None and r0["traffic"] is None and r0["hbm_frac"] == r["hbm_frac"]
+    assert r0["lds_busy_frac"] is None
