@@ -47,7 +47,7 @@ typedef enum {
     NGDBF_ENOMEM = -2,       /* device or host allocation failed             */
     NGDBF_EDEVICE = -3,      /* HIP runtime error                             */
     NGDBF_EUNSUPPORTED = -4, /* valid, but outside what the kernels support  */
-    NGDBF_EBUSY = -5         /* the frame queue a launch would take is still
+    NGDBF_EBUSY = -5         /* every frame queue a launch could take is
                                 held by a launch in flight (see ngdbf_decode) */
 } ngdbf_status;
 
@@ -150,16 +150,17 @@ ngdbf_status ngdbf_code_info(const ngdbf_code *code, int32_t *n, int32_t *m,
  * itself when it ends).  Direct launches take queues from one ring of 1024,
  * launches recorded under stream capture from another ring of 1024, so a
  * graph's launches never share a queue with direct launches.  An event
- * recorded after each direct launch marks its queue free again: a direct
- * launch that would take a queue still held by a launch in flight (1024
- * launches queued on streams and not yet finished) returns NGDBF_EBUSY and
- * launches nothing.  At most 1024 recorded launches may belong to graphs
+ * recorded after each direct launch marks its queue free again; a direct
+ * launch takes the next free queue of its ring (passing over those still
+ * held, e.g. by one long launch while many short ones come and go on other
+ * streams) and returns NGDBF_EBUSY, launching nothing, only when all 1024
+ * are held by launches queued on streams and not yet finished.  At most 1024 recorded launches may belong to graphs
  * replayed at the same time; a captured graph must not be replayed on two
  * streams at the same time.  With trace rows, the rows
  * are cleared by a kernel on `stream` before the decode (no memset node
  * under capture).
  * Errors: NGDBF_EINVAL (NULL pointers with n_frames > 0, parameters out of
- * range), NGDBF_EBUSY (its queue still held, see above),
+ * range), NGDBF_EBUSY (every queue held, see above),
  * NGDBF_EDEVICE (launch failure, or an earlier fault reported now).
  */
 ngdbf_status ngdbf_decode(const ngdbf_code *code, const void *y, int64_t n_frames,
@@ -311,7 +312,7 @@ typedef struct {
  * ngdbf_decode), so a batch holds at most 1024 jobs.
  * jobs: host array [n_jobs]; all codes on the current device.
  * Errors: NGDBF_EINVAL (any job invalid, n_jobs < 0 or above 1024),
- * NGDBF_EBUSY (a job's queue still held by a launch in flight), NGDBF_EDEVICE.
+ * NGDBF_EBUSY (no free queue for a job, see ngdbf_decode), NGDBF_EDEVICE.
  */
 ngdbf_status ngdbf_decode_batch(const ngdbf_job *jobs, int32_t n_jobs, void *stream);
 

@@ -161,9 +161,9 @@ using ngdbf_host::Shape;
 // ring of kCapturedSlots of their own, so that a graph's queues are never
 // those of direct launches running beside its replays.  Launches in flight
 // together take different queues: an event recorded after each direct launch
-// marks its queue free again, and a launch whose ring slot is still held
-// fails with NGDBF_EBUSY instead of sharing it.  A graph must not be replayed
-// on two streams at the same time.
+// marks its queue free again, a launch passes over ring slots that are still
+// held, and one that finds all of them held fails with NGDBF_EBUSY instead of
+// sharing one.  A graph must not be replayed on two streams at the same time.
 constexpr int kQueueSlots = 1024;
 constexpr int kCapturedSlots = 1024;
 
@@ -274,21 +274,28 @@ int take_queue(int dev, bool captured, unsigned long long **queue, int *slot) {
     *slot = -1;
     return NGDBF_OK;
   }
-  const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
-  // an earlier error is left for the caller to report; the query's own
-  // "not ready" is not an error and is cleared here
-  if (hipPeekAtLastError() == hipSuccess) {
-    const hipError_t q = hipEventQuery(st.queue_done[i]);
-    if (q == hipErrorNotReady) {
-      (void)hipGetLastError();
-      return fail(NGDBF_EBUSY, "all %d frame queues of device %d are held by launches in flight",
-                  kQueueSlots, dev);
+  // An earlier error is left for the caller to report (the slot is then taken
+  // unchecked).  A slot whose launch is still running is passed over: one long
+  // launch may hold its queue while a thousand short ones on other streams
+  // come and go.  Every probe draws a fresh ring index, so a slot goes to two
+  // takers only if a full turn of the ring passes between them.
+  const bool check = hipPeekAtLastError() == hipSuccess;
+  for (int probe = 0; probe < kQueueSlots; ++probe) {
+    const uint32_t i = st.next_queue.fetch_add(1u) % (uint32_t)kQueueSlots;
+    if (check) {
+      const hipError_t q = hipEventQuery(st.queue_done[i]);
+      if (q == hipErrorNotReady) {
+        (void)hipGetLastError();  // "not ready" is not an error
+        continue;
+      }
+      if (q != hipSuccess) return fail(NGDBF_EDEVICE, "frame queue event: %s", hipGetErrorString(q));
     }
-    if (q != hipSuccess) return fail(NGDBF_EDEVICE, "frame queue event: %s", hipGetErrorString(q));
+    *queue = st.queues + (size_t)ngdbf::kQueueWords * i;
+    *slot = (int)i;
+    return NGDBF_OK;
   }
-  *queue = st.queues + (size_t)ngdbf::kQueueWords * i;
-  *slot = (int)i;
-  return NGDBF_OK;
+  return fail(NGDBF_EBUSY, "all %d frame queues of device %d are held by launches in flight",
+              kQueueSlots, dev);
 }
 
 // mark a direct launch's queue as held until the work queued on s so far ends

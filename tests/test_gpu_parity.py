@@ -306,6 +306,69 @@ def test_graph_replays_beside_direct_launches(torch_dev):
     del g
 
 
+def test_long_launch_beside_many_short_ones(torch_dev):
+    """A direct launch passes over ring queues still held: eight long decodes
+    queued on one stream (a C4000 frame that never converges, 65535 rounds
+    each) hold their queues while 1100 one-frame decodes on another stream
+    take and free the rest of the ring, more than it holds; every short decode
+    equals the oracle and every long one the same decode run alone.  The short
+    decodes go to a stream that runs beside the long ones (streams can share a
+    hardware queue, whose launches then run one after another)."""
+    import time
+
+    torch = torch_dev
+    c4, dc4 = dev_code("C4000")
+    sig4 = np.float32(channel.sigma_from_ebn0(0.0, c4.rate))
+    y4 = channel.bpsk_awgn(1, c4.n, sig4, seed=83)
+    p_long = ng.Params(w=0.75, theta=-0.6, lam=1.0, eta=0.9, ymax=2.5, t_max=65535, smooth_window=0)
+    y4_dev = torch.from_numpy(y4).cuda()
+    c, dc = dev_code("C96")
+    sig = np.float32(channel.sigma_from_ebn0(3.0, c.rate))
+    y = channel.bpsk_awgn(1100, c.n, sig, seed=84)
+    y_dev = torch.from_numpy(y).cuda()
+    gp = ng.Params(**P_C1.__dict__)
+    outs = [ng.alloc_outputs(dc, 1, "cuda") for _ in range(1100)]
+    probe = ng.alloc_outputs(dc, 1, "cuda")
+    torch.cuda.synchronize()
+    long_s = torch.cuda.Stream()
+    candidates = [torch.cuda.Stream() for _ in range(4)]
+    say("eight 65535-round C4000 decodes beside 1100 one-frame C96 decodes")
+    t0 = time.perf_counter()
+    longs = [ng.decode(dc4, y4_dev, float(sig4), p_long, 85, stream=long_s) for _ in range(8)]
+    long_done = torch.cuda.Event()
+    long_done.record(long_s)
+    short_s = None
+    for cand in candidates:
+        ng.decode(dc, y_dev[:1], float(sig), gp, 86, out=probe, stream=cand)
+        cand.synchronize()
+        if not long_done.query():
+            short_s = cand
+            break
+    if short_s is None:
+        torch.cuda.synchronize()
+        pytest.skip("no stream ran beside the long decodes")
+    for i in range(1100):
+        # frame i has its own noise key (seed, i), as in one decode of all 1100
+        ng.decode(dc, y_dev[i:i + 1], float(sig), gp, 86, frame_base=i, out=outs[i], stream=short_s)
+        if i % 100 == 99:
+            short_s.synchronize()
+    short_s.synchronize()
+    t_short = time.perf_counter() - t0
+    exercised = not long_done.query()
+    torch.cuda.synchronize()
+    t_long = time.perf_counter() - t0
+    say(f"short decodes done after {t_short * 1e3:.1f} ms, long decodes after {t_long * 1e3:.1f} ms")
+    assert exercised, "the long decodes ended before the short ones wrapped the ring"
+    r = oracle.decode(c, y, sig, P_C1, 86)
+    assert (torch.cat([o.iters for o in outs]).cpu().numpy() == r.iters).all()
+    assert (torch.cat([o.bits for o in outs]).cpu().numpy() == r.bits).all()
+    alone = ng.decode(dc4, y4_dev, float(sig4), p_long, 85)
+    torch.cuda.synchronize()
+    assert int(alone.iters[0]) == 65535 and not bool(alone.converged[0])
+    for o in longs:
+        assert torch.equal(o.bits, alone.bits) and torch.equal(o.iters, alone.iters)
+
+
 def test_settle_statistics(torch_dev):
     """The settle-test counters: every round of every frame evaluates ceil(n/2)
     pairs, a minority of them is transformed, and the decode is unchanged."""
