@@ -118,6 +118,12 @@ def test_sincos_exhaustive_against_libm(oracle_lib):
     assert np.abs(c.astype(np.float64) - np.cos(phi)).max() < 2.0**-23
     assert np.abs(s.astype(np.float64) - np.sin(phi)).max() < 2.0**-23
     assert np.abs(c).max() <= 1.0 and np.abs(s).max() <= 1.0
+    # the quarter turn (the angle word's top two bits) fixes the signs, zeros
+    # aside: cos >= 0 in quarters 0 and 3, <= 0 in 1 and 2; sin >= 0 in 0 and
+    # 1, <= 0 in 2 and 3
+    q = np.arange(1 << 24, dtype=np.uint32) >> 22
+    assert not (c[(q == 0) | (q == 3)] < 0).any() and not (c[(q == 1) | (q == 2)] > 0).any()
+    assert not (s[q <= 1] < 0).any() and not (s[q >= 2] > 0).any()
 
 
 def test_noise_is_standard_normal(oracle_lib):
