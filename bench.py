@@ -331,10 +331,18 @@ def run_mix4(args) -> int:
         if it["name"] in fixed:
             ng.ngdbf_code_set_shape(it["dc"].handle, *fixed[it["name"]])
         elif not args.no_mix_autotune:
-            n_s = min(it["frames"], 1 << 17)  # several times the resident frames
+            # a sample of its own (same code, parameters and Eb/N0 range, other
+            # channel and decoder seeds), several times the resident frames
+            n_s = min(it["frames"], 1 << 17)
+            idx = [m[0] for m in MIX4].index(it["name"])
+            sig_s = torch.from_numpy(channel.frame_sigmas(n_s, 2.0, 5.0, it["c"].rate, seed=900 + idx)).cuda()
+            y_s = ng.channel(it["c"].n, n_s, sig_s, seed=sweep.channel_seed(920 + idx))
             t0 = time.perf_counter()
-            ng.autotune(it["dc"], it["y"][:n_s], it["sig"][:n_s], it["p"], it["seed"])
-            autotune_ms[it["name"]] = {"sample_frames": n_s, "wall_ms": (time.perf_counter() - t0) * 1e3}
+            ng.autotune(it["dc"], y_s, sig_s, it["p"], 940 + idx)
+            del y_s, sig_s
+            autotune_ms[it["name"]] = {"sample_frames": n_s, "wall_ms": (time.perf_counter() - t0) * 1e3,
+                                       "sample": "a tuning sample, not frames of the batch: Eb/N0 U[2,5] dB, channel seed "
+                                                 f"{920 + idx}, decoder seed {940 + idx}"}
         it["shape"] = list(ng.ngdbf_code_get_shape(it["dc"].handle, it["p"].c(ng.NGDBF_Y_F32)))
     jobs = [ng.job(it["dc"], it["y"], it["sig"], it["p"], it["seed"], it["out"]) for it in items]
     ng.ngdbf_decode_batch(jobs, None)
