@@ -1,8 +1,9 @@
 """GPU parity for the parameter corners and full-size configurations the
 measurements use: thresholds theta >= 0 with adaptation, per-frame sigma
 arrays holding zeros and negative values, the (6,32) code's searched
-parameter set and the N=4000 SM-NGDBF point sampled from full-size launches,
-and the binary32 decoder against the binary64 oracle at the headline point.
+parameter set, the N=4000 SM-NGDBF point and the default benchmark's 2^22-frame
+four-code batch sampled from full-size launches, and the binary32 decoder
+against the binary64 oracle at the headline point.
 
 Integer results (decoded words, iteration counts, flags, flip masks) must be
 identical to the oracle's; the binary64 comparison is statistical (FER and
@@ -190,6 +191,54 @@ def test_c4000_sm_ngdbf_full_size(torch_dev):
     torch.cuda.synchronize()
     sampled_blocks(torch, "C4000", y, sig, p, 2035, out, F, block=32)
     del y, out
+    torch.cuda.empty_cache()
+
+
+def test_mix4_full_size_batch_sampled(torch_dev):
+    """The default benchmark's batch as bench.py times it: C96 : C1008 : C2048
+    : C4000 = 2^21 : 2^20 : 2^19 : 2^19 frames, per-frame Eb/N0 uniform in
+    2..5 dB, per-code parameters, frames from the device channel, each code at
+    the shape the autotuner picks on a tuning sample of its own, one
+    ngdbf_decode_batch; the first, a middle and the last frames of every code
+    against the oracle."""
+    import bench
+    from paper_1402_2773_amd import sweep
+
+    torch = torch_dev
+    items = []
+    for idx, (name, frames, params) in enumerate(bench.MIX4):
+        c = codes.named_code(name)
+        dc = ng.Code.from_ldpc(c)  # a handle of its own: the tuned shape stays on it
+        p = ng.Params(**params)
+        n_s = min(frames, 1 << 17)
+        sig_s = torch.from_numpy(channel.frame_sigmas(n_s, 2.0, 5.0, c.rate, seed=900 + idx)).cuda()
+        y_s = ng.channel(c.n, n_s, sig_s, seed=sweep.channel_seed(920 + idx))
+        best, _ = ng.autotune(dc, y_s, sig_s, p, 940 + idx)
+        del y_s, sig_s
+        sig_h = channel.frame_sigmas(frames, 2.0, 5.0, c.rate, seed=300 + idx)
+        sig = torch.from_numpy(sig_h).cuda()
+        y = ng.channel(c.n, frames, sig, seed=sweep.channel_seed(320 + idx))
+        say(name, frames, "frames at the tuned shape", list(best))
+        items.append(dict(c=c, dc=dc, y=y, sig=sig, sig_h=sig_h, params=params, p=p, seed=320 + idx,
+                          frames=frames, out=ng.alloc_outputs(dc, frames, "cuda")))
+    jobs = [ng.job(it["dc"], it["y"], it["sig"], it["p"], it["seed"], it["out"]) for it in items]
+    say("one batch of 2^22 frames")
+    ng.ngdbf_decode_batch(jobs, None)
+    torch.cuda.synchronize()
+    block = 16
+    for it in items:
+        F, c = it["frames"], it["c"]
+        for start in (0, F // 2 + 5, F - block):
+            yh = it["y"][start:start + block].cpu().numpy()
+            r = oracle.decode(c, yh, it["sig_h"][start:start + block], oracle.Params(**it["params"]),
+                              it["seed"], frame_base=start, threads=8)
+            o = it["out"]
+            assert (o.iters[start:start + block].cpu().numpy() == r.iters).all(), f"{c.name} iters {start}"
+            assert (o.converged[start:start + block].cpu().numpy() == r.converged).all()
+            assert (o.bits[start:start + block].cpu().numpy() == r.bits).all(), f"{c.name} bits {start}"
+    for it in items:
+        it["dc"].close()
+    del items, jobs
     torch.cuda.empty_cache()
 
 
