@@ -207,7 +207,9 @@ def hbm_bytes_per_frame(code, yfmt: str, per_frame_sigma: bool = False) -> int:
 
 
 def host_cpu():
-    """Host threads available to this process and the CPU model name."""
+    """Host threads available to this process (its CPU affinity, which on a
+    shared host is its share of the machine's logical CPUs) and the CPU model
+    name."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -251,7 +253,7 @@ def cpu_baseline(code, y_host, sigma, params, seed, budget_s: float):
     cores, model = host_cpu()
     fps, n1, dt, iters = oracle_rate(code, y_host, sigma, params, seed, budget_s, cores)
     return {"value": fps * code.k_info / 1e9, "unit": "Gbit/s", "cores": cores, "cpu_model": model,
-            "kind": "oracle",
+            "host_logical_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{n1} of the workload's frames (same code, SNR, parameters), {dt:.1f} s on "
                       f"{cores} host threads",
             "edge_updates_per_s": iters * code.nnz / dt}
@@ -457,7 +459,7 @@ def run_mix4(args) -> int:
             sample.append(f"{it['name']}: {n1} frames in {dt:.1f} s")
         result["cpu_baseline"] = {
             "value": info_bits / cpu_s / 1e9, "unit": "Gbit/s", "cores": cores, "cpu_model": model,
-            "kind": "oracle",
+            "host_logical_cpus": os.cpu_count(), "kind": "oracle",
             "sample": "the first frames of every code of the mix (same inputs, parameters, noise keys); "
                       + "; ".join(sample) + f"; whole-mix time extrapolated per code on {cores} host threads"}
     print(json.dumps(result), flush=True)
