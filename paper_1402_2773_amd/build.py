@@ -17,9 +17,11 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libngdbf.so")
-SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("decode.hip", "decode_ext_multi.hip", "decode_ext_single.hip",
-                     "decode_ext_switch.hip", "decode_ext_packed.hip", "channel.hip", "probe.hip", "server.cpp")]
+# (source, extra flags, object name): the extended decoder families are one
+# source compiled once per family, so that their kernel sets build in parallel
+UNITS = [("decode.hip", [], "decode"),
+         *[("decode_ext.hip", [f"-DNGDBF_EXT_FAMILY={k}"], f"decode_ext{k}") for k in range(4)],
+         ("channel.hip", [], "channel"), ("probe.hip", [], "probe"), ("server.cpp", [], "server")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("NGDBF_ARCH", "gfx950")
 
@@ -36,9 +38,9 @@ def build(verbose: bool = False) -> str:
     """Compile every source to an object (in parallel), then link the library."""
     with tempfile.TemporaryDirectory(prefix="ngdbf_build_") as tmpdir:
         procs, objs = [], []
-        for src in SOURCES:
-            obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
-            cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        for src, extra, name in UNITS:
+            obj = os.path.join(tmpdir, name + ".o")
+            cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(HERE, "csrc", src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((subprocess.Popen(cmd), cmd))

@@ -2,8 +2,7 @@
 // validation, the multi-bit binary32 kernels' instantiations, the noise
 // probes and the C ABI of ngdbf.h.  The kernel itself is in kernel.h; the
 // extended decoders (single-bit, mode switching, quantized, noise reuse) are
-// instantiated in decode_ext_multi.hip, decode_ext_single.hip and
-// decode_ext_switch.hip.
+// instantiated in decode_ext.hip, one object per family.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>

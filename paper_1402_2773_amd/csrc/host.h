@@ -65,9 +65,8 @@ int dispatch(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev, h
   return fail(NGDBF_EUNSUPPORTED, "no kernel for %d waves x %d quads", sh.wpf, sh.qpl);
 }
 
-// The extended decoders, one translation unit per family
-// (decode_ext_multi.hip, decode_ext_single.hip, decode_ext_switch.hip,
-// decode_ext_packed.hip).
+// The extended decoders, instantiated in decode_ext.hip (one object per
+// family).
 int dispatch_ext_multi(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
                        hipStream_t s, int y_format, bool trace);
 int dispatch_ext_single(const Shape &sh, const ngdbf::DecodeArgs &a, size_t lds, int dev,
