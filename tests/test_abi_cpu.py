@@ -36,6 +36,20 @@ def test_library_exports_every_declared_symbol(L):
         assert hasattr(L, name), name
 
 
+def test_build_compiles_every_source_and_decoder_family():
+    """Every HIP/C++ source under csrc is a build unit, and the extended
+    decoder source is compiled once per family (the library holds all four
+    families' dispatchers)."""
+    from paper_1402_2773_amd import build
+
+    csrc = os.path.join(ROOT, "paper_1402_2773_amd", "csrc")
+    sources = {f for f in os.listdir(csrc) if f.endswith((".hip", ".cpp"))}
+    assert sources == {u[0] for u in build.UNITS}
+    fams = sorted(x for src, flags, _ in build.UNITS if src == "decode_ext.hip" for x in flags)
+    assert fams == [f"-DNGDBF_EXT_FAMILY={k}" for k in range(4)]
+    assert len({u[2] for u in build.UNITS}) == len(build.UNITS)  # one object name each
+
+
 def test_create_code_rejects_bad_tables(L):
     with pytest.raises(ng.NgdbfError, match="row_ptr"):
         ng.ngdbf_create_code(4, 2, [1, 2, 4], [0, 1, 2, 3])
